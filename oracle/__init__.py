@@ -1,0 +1,197 @@
+"""CPU oracle for all pairs of geodesic distances -- TEST INFRASTRUCTURE ONLY.
+
+This package wraps ``gapd_oracle.c``, a plain C implementation of what the
+GPU library computes, written from the paper (Noyel, Angulo, Jeulin, "Fast
+computation of all pairs of geodesic distances"): Dijkstra propagations,
+Floyd-Warshall for tiny images, the naive method, the geodesic centroid and
+extrema list, and the filling-rate method with its redundancy fill.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import it.  It shares no code with the GPU library and never imports it;
+the GPU library never imports this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gapd_oracle.c")
+_LIB = os.environ.get("GAPD_ORACLE_LIB") or os.path.join(_HERE, "libgapd_oracle.so")
+
+W_SUM = 0
+W_1PL1 = 1
+TRUNCATED = 2
+
+_lib = None
+
+
+def build(force: bool = True, out: str = None, mutant: int = 0) -> str:
+    """Compile the oracle with gcc (plain -O3, portable code, OpenMP).
+
+    ``mutant`` > 0 plants one of the deliberate mistakes of ``gapd_oracle.c``
+    (used only by the test that checks the pins reject them)."""
+    out = out or _LIB
+    if force or not os.path.exists(out):
+        cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+               f"-DORACLE_MUTANT={int(mutant)}", "-o", out + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+    return out
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int, ctypes.c_int64
+        sigs = {
+            "gapd_oracle_dijkstra": [P, i32, i32, i32, i32, i32, P, i64, P],
+            "gapd_oracle_floyd": [P, i32, i32, i32, i32, i32, P],
+            "gapd_oracle_rows": [P, i32, i32, i32, i32, i32, P, i64, P, i32],
+            "gapd_oracle_naive": [P, i32, i32, i32, i32, i32, P, i32],
+            "gapd_oracle_parents": [P, i32, i32, i32, i32, i32, P, P],
+            "gapd_oracle_extrema": [P, i32, i32, i32, i32, i32, P, P, P, P],
+            "gapd_oracle_filling_rate": [P, i32, i32, i32, i32, i32, P, P, P, P, P, P, i64],
+        }
+        for name, args in sigs.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _img(image: np.ndarray):
+    image = np.ascontiguousarray(image, dtype=np.uint8)
+    if image.ndim == 2:
+        H, W = image.shape
+        C = 1
+    elif image.ndim == 3:
+        H, W, C = image.shape
+    else:
+        raise ValueError("image must be (H, W) or (H, W, C)")
+    return image, H, W, C
+
+
+def _check(st: int, name: str):
+    if st not in (0, TRUNCATED):
+        raise RuntimeError(f"{name} failed with status {st}")
+    return st
+
+
+def default_wmode(image: np.ndarray) -> int:
+    return W_SUM if (image.ndim == 2 or image.shape[2] == 1) else W_1PL1
+
+
+def dijkstra(image, seeds, conn=4, wmode=None) -> np.ndarray:
+    """Distances (int64, length N) from the seed pixels (all at distance 0)."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    seeds = np.ascontiguousarray(np.atleast_1d(seeds), dtype=np.int64)
+    out = np.empty(H * W, dtype=np.int64)
+    _check(_load().gapd_oracle_dijkstra(_ptr(image), H, W, C, conn, wmode, _ptr(seeds), seeds.size,
+                                        _ptr(out)), "dijkstra")
+    return out
+
+
+def floyd(image, conn=4, wmode=None) -> np.ndarray:
+    """All-pairs distances (int64 N x N) by Floyd-Warshall; N <= 1024."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    out = np.empty((H * W, H * W), dtype=np.int64)
+    _check(_load().gapd_oracle_floyd(_ptr(image), H, W, C, conn, wmode, _ptr(out)), "floyd")
+    return out
+
+
+def rows(image, sources, conn=4, wmode=None, threads=None) -> np.ndarray:
+    """Distance rows (int32, K x N) for the given sources."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    src = np.ascontiguousarray(np.atleast_1d(sources), dtype=np.int32)
+    out = np.empty((src.size, H * W), dtype=np.int32)
+    threads = threads or os.cpu_count() or 1
+    _check(_load().gapd_oracle_rows(_ptr(image), H, W, C, conn, wmode, _ptr(src), src.size, _ptr(out),
+                                    threads), "rows")
+    return out
+
+
+def naive(image, conn=4, wmode=None, threads=None) -> np.ndarray:
+    """The naive method: the full N x N int32 distances array."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    out = np.empty((H * W, H * W), dtype=np.int32)
+    threads = threads or os.cpu_count() or 1
+    _check(_load().gapd_oracle_naive(_ptr(image), H, W, C, conn, wmode, _ptr(out), threads), "naive")
+    return out
+
+
+def parents(image, dist, conn=4, wmode=None) -> np.ndarray:
+    """Canonical geodesic-tree parents (int32, -1 at the root) from final distances."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    dist = np.ascontiguousarray(dist, dtype=np.int64)
+    out = np.empty(H * W, dtype=np.int32)
+    _check(_load().gapd_oracle_parents(_ptr(image), H, W, C, conn, wmode, _ptr(dist), _ptr(out)), "parents")
+    return out
+
+
+@dataclass
+class Extrema:
+    centroid: int
+    d_edge: np.ndarray
+    d_c: np.ndarray
+    rank: np.ndarray
+
+
+def extrema(image, conn=4, wmode=None) -> Extrema:
+    """Geodesic centroid, the two setup propagations and the extrema ranks."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    N = H * W
+    c = np.zeros(1, dtype=np.int32)
+    de = np.empty(N, dtype=np.int64)
+    dc = np.empty(N, dtype=np.int64)
+    rk = np.empty(N, dtype=np.int32)
+    _check(_load().gapd_oracle_extrema(_ptr(image), H, W, C, conn, wmode, _ptr(c), _ptr(de), _ptr(dc),
+                                       _ptr(rk)), "extrema")
+    return Extrema(int(c[0]), de, dc, rk)
+
+
+@dataclass
+class FillingRate:
+    D: np.ndarray            # N x N int32 (partly written if truncated)
+    sequence: np.ndarray     # sources, one per propagation
+    filled: np.ndarray       # a(t): filled pairs after each propagation
+    n_prop: int              # propagations in the loop (setup's 2 not included)
+    centroid: int
+    rank: np.ndarray
+    truncated: bool
+
+
+def filling_rate(image, conn=4, wmode=None, max_steps: int = -1) -> FillingRate:
+    """The filling-rate method; ``max_steps`` bounds the loop (for timing samples)."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    N = H * W
+    D = np.full((N, N), -1, dtype=np.int32)
+    seq = np.full(N, -1, dtype=np.int32)
+    a = np.zeros(N, dtype=np.int64)
+    n = np.zeros(1, dtype=np.int64)
+    c = np.zeros(1, dtype=np.int32)
+    rk = np.empty(N, dtype=np.int32)
+    st = _check(_load().gapd_oracle_filling_rate(_ptr(image), H, W, C, conn, wmode, _ptr(D), _ptr(seq), _ptr(a),
+                                                 _ptr(n), _ptr(c), _ptr(rk), int(max_steps)), "filling_rate")
+    k = int(n[0])
+    return FillingRate(D, seq[:k].copy(), a[:k].copy(), k, int(c[0]), rk, st == TRUNCATED)

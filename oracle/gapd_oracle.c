@@ -1,0 +1,400 @@
+/*
+ * gapd_oracle.c -- plain, slow, CPU reference for all pairs of geodesic
+ * distances on a pixel grid (Noyel, Angulo, Jeulin, "Fast computation of all
+ * pairs of geodesic distances").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code, header, table or helper
+ * with the GPU library, and the GPU library never calls it.
+ *
+ * What it computes, each function citing the passage it follows:
+ *   - edge weights: the "sum of grey levels" pseudo-metric d_+ (Section 2, eq.
+ *     distance_somme) and, for multiband images, 1 + L1 spectral difference
+ *     (the paper's Section 5 leaves the multiband pseudo-metric open; this is
+ *     the reading used throughout);
+ *   - geodesic distance = minimum over paths of the summed edge weights
+ *     (Section 2, eqs. temps and distance), by Dijkstra with a binary heap,
+ *     and independently by Floyd-Warshall for tiny images;
+ *   - the naive method: one propagation per pixel (Section 1);
+ *   - the filling-rate method (Section 3.4, algorithm "filling"), with the
+ *     geodesic centroid and the decreasing list of geodesic extrema
+ *     (Section 3.3), and the redundancy fill along geodesic trees
+ *     (Section 2, Property 1).
+ *
+ * Readings of the paper taken here (where it is silent or ambiguous):
+ *   - pixel index i = y*W + x; no wrap-around at the image border;
+ *   - 4-neighbours in ascending index order: up, left, right, down;
+ *     8-neighbours: (-1,-1) (-1,0) (-1,+1) (0,-1) (0,+1) (+1,-1) (+1,0) (+1,+1);
+ *     diagonal edges use the same pseudo-metric (no Euclidean factor);
+ *   - geodesic tree: the parent of v != root is the smallest-index neighbour q
+ *     with d(q) + w(q,v) == d(v), computed from the final distances;
+ *   - the tree fills exactly its ancestor/descendant pairs, both orientations;
+ *   - "propagation from the edges": every border pixel starts at distance 0;
+ *     the centroid is the first pixel (smallest index) of maximal distance;
+ *   - the extrema list orders pixels by decreasing distance from the
+ *     centroid, ties by increasing index; "Ext[x]" is x's position (rank);
+ *   - the filling rate of a point is carried as the integer count of filled
+ *     entries of its row (diagonal included), which has the same argmin.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+#define OR_ERANGE (-4)
+#define OR_TRUNCATED 2
+
+#define OR_W_SUM 0
+#define OR_W_1PL1 1
+
+/* ORACLE_MUTANT plants one deliberate mistake (build with -DORACLE_MUTANT=k);
+ * the test suite builds each mutant and checks that its pins reject it. */
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
+typedef struct {
+    const uint8_t *img; /* H*W*C bytes, HWC row-major */
+    int H, W, C, conn, wmode;
+    int64_t N;
+} or_graph;
+
+static int or_check(const or_graph *g) {
+    if (!g->img || g->H < 1 || g->W < 1 || g->C < 1) return OR_EINVAL;
+    if (g->conn != 4 && g->conn != 8) return OR_EINVAL;
+    if (g->wmode == OR_W_SUM && g->C != 1) return OR_EINVAL;
+    if (g->wmode != OR_W_SUM && g->wmode != OR_W_1PL1) return OR_EINVAL;
+    return OR_OK;
+}
+
+/* Edge weight between neighbouring pixels p and q.  d_+ is Section 2, eq.
+ * distance_somme; the multiband weight is 1 + sum over bands |f_b(p)-f_b(q)|. */
+static int64_t or_weight(const or_graph *g, int64_t p, int64_t q) {
+    if (g->wmode == OR_W_SUM) {
+        if (ORACLE_MUTANT == 2) return 2 * (int64_t)g->img[p];
+        return (int64_t)g->img[p] + (int64_t)g->img[q];
+    }
+    int64_t s = ORACLE_MUTANT == 8 ? 0 : 1;
+    for (int b = 0; b < g->C; ++b) {
+        int64_t a = g->img[p * g->C + b], c = g->img[q * g->C + b];
+        s += a > c ? a - c : c - a;
+    }
+    return s;
+}
+
+/* Neighbours of p (Section 2, eqs. voisinage_1/2) in ascending index order. */
+static int or_neighbours(const or_graph *g, int64_t p, int64_t *out) {
+    int y = (int)(p / g->W), x = (int)(p % g->W), n = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            if (g->conn == 4 && dy != 0 && dx != 0) continue;
+            int yy = y + dy, xx = x + dx;
+            if (yy < 0 || yy >= g->H || xx < 0 || xx >= g->W) continue;
+            out[n++] = (int64_t)yy * g->W + xx;
+        }
+    return n;
+}
+
+/* ---- binary heap of (distance, node), lazy deletion ---------------------------------- */
+typedef struct { int64_t d; int64_t v; } or_item;
+typedef struct { or_item *a; int64_t n, cap; } or_heap;
+
+static int or_push(or_heap *h, int64_t d, int64_t v) {
+    if (h->n == h->cap) {
+        int64_t nc = h->cap ? 2 * h->cap : 1024;
+        or_item *na = (or_item *)realloc(h->a, (size_t)nc * sizeof(or_item));
+        if (!na) return OR_ENOMEM;
+        h->a = na; h->cap = nc;
+    }
+    int64_t i = h->n++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h->a[p].d <= d) break;
+        h->a[i] = h->a[p];
+        i = p;
+    }
+    h->a[i].d = d; h->a[i].v = v;
+    return OR_OK;
+}
+
+static or_item or_pop(or_heap *h) {
+    or_item top = h->a[0], last = h->a[--h->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        int64_t md = last.d;
+        if (l < h->n && h->a[l].d < md) { m = l; md = h->a[l].d; }
+        if (r < h->n && h->a[r].d < md) { m = r; }
+        if (m == i) break;
+        h->a[i] = h->a[m];
+        i = m;
+    }
+    if (h->n > 0) h->a[i] = last;
+    return top;
+}
+
+/* Geodesic propagation (Section 1: "computing the geodesic distance from one
+ * pixel to all others"): Dijkstra from a set of seeds at distance 0. */
+static int or_dijkstra(const or_graph *g, const int64_t *seeds, int64_t nseeds, int64_t *dist) {
+    const int64_t INF = INT64_MAX / 4;
+    for (int64_t i = 0; i < g->N; ++i) dist[i] = INF;
+    or_heap h = {0, 0, 0};
+    for (int64_t k = 0; k < nseeds; ++k) {
+        if (seeds[k] < 0 || seeds[k] >= g->N) { free(h.a); return OR_EINVAL; }
+        dist[seeds[k]] = 0;
+        if (or_push(&h, 0, seeds[k])) { free(h.a); return OR_ENOMEM; }
+    }
+    int64_t nb[8];
+    while (h.n > 0) {
+        or_item it = or_pop(&h);
+        if (it.d != dist[it.v]) continue; /* stale entry */
+        int k = or_neighbours(g, it.v, nb);
+        for (int j = 0; j < k; ++j) {
+            int64_t nd = it.d + or_weight(g, it.v, nb[j]);
+            if (nd < dist[nb[j]]) {
+                dist[nb[j]] = nd;
+                if (or_push(&h, nd, nb[j])) { free(h.a); return OR_ENOMEM; }
+            }
+        }
+    }
+    free(h.a);
+    return OR_OK;
+}
+
+static int or_graph_init(or_graph *g, const uint8_t *img, int H, int W, int C, int conn, int wmode) {
+    g->img = img; g->H = H; g->W = W; g->C = C; g->conn = conn; g->wmode = wmode;
+    g->N = (int64_t)H * W;
+    return or_check(g);
+}
+
+/* ---- exported entry points ---------------------------------------------------------- */
+
+/* Multi-seed propagation; dist receives N int64 distances. */
+int gapd_oracle_dijkstra(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                         const int64_t *seeds, int64_t nseeds, int64_t *dist) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    if (!dist || nseeds < 1 || !seeds) return OR_EINVAL;
+    return or_dijkstra(&g, seeds, nseeds, dist);
+}
+
+/* Floyd-Warshall on the same graph (textbook all-pairs shortest paths), int64,
+ * for tiny images only: D receives N*N entries. */
+int gapd_oracle_floyd(const uint8_t *img, int H, int W, int C, int conn, int wmode, int64_t *D) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    if (!D || g.N > 1024) return OR_EINVAL;
+    const int64_t N = g.N, INF = INT64_MAX / 4;
+    for (int64_t i = 0; i < N * N; ++i) D[i] = INF;
+    int64_t nb[8];
+    for (int64_t p = 0; p < N; ++p) {
+        D[p * N + p] = 0;
+        int k = or_neighbours(&g, p, nb);
+        for (int j = 0; j < k; ++j) D[p * N + nb[j]] = or_weight(&g, p, nb[j]);
+    }
+    for (int64_t k = 0; k < N; ++k)
+        for (int64_t i = 0; i < N; ++i) {
+            int64_t dik = D[i * N + k];
+            if (dik >= INF) continue;
+            for (int64_t j = 0; j < N; ++j) {
+                int64_t c = dik + D[k * N + j];
+                if (c < D[i * N + j]) D[i * N + j] = c;
+            }
+        }
+    return OR_OK;
+}
+
+/* Rows of the distances array for K given sources (one propagation each);
+ * out receives K*N int32.  The naive method (Section 1) is sources = 0..N-1. */
+int gapd_oracle_rows(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                     const int32_t *sources, int64_t K, int32_t *out, int nthreads) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    if (!out || K < 0 || (K > 0 && !sources)) return OR_EINVAL;
+    for (int64_t k = 0; k < K; ++k)
+        if (sources[k] < 0 || sources[k] >= g.N) return OR_EINVAL;
+    int err = OR_OK;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int64_t *dist = (int64_t *)malloc((size_t)g.N * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t k = 0; k < K; ++k) {
+            if (!dist) { err = OR_ENOMEM; continue; }
+            int64_t s = sources[k];
+            int e = or_dijkstra(&g, &s, 1, dist);
+            if (e) { err = e; continue; }
+            for (int64_t v = 0; v < g.N; ++v) {
+                if (dist[v] > INT32_MAX) { err = OR_ERANGE; break; }
+                out[k * g.N + v] = (int32_t)dist[v];
+            }
+        }
+        free(dist);
+    }
+    return err;
+}
+
+/* The naive method (Section 1): N propagations, one per pixel; D is N*N int32. */
+int gapd_oracle_naive(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                      int32_t *D, int nthreads) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    int32_t *src = (int32_t *)malloc((size_t)g.N * sizeof(int32_t));
+    if (!src) return OR_ENOMEM;
+    for (int64_t i = 0; i < g.N; ++i) src[i] = (int32_t)i;
+    st = gapd_oracle_rows(img, H, W, C, conn, wmode, src, g.N, D, nthreads);
+    free(src);
+    return st;
+}
+
+/* Geodesic tree of a propagation (Section 2: root, nodes, leaves): parent of
+ * v is the smallest-index neighbour q with dist(q) + w(q,v) == dist(v); the
+ * root (dist 0, a seed) gets parent -1.  Computed from the final distances. */
+int gapd_oracle_parents(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                        const int64_t *dist, int32_t *parent) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    int64_t nb[8];
+    for (int64_t v = 0; v < g.N; ++v) {
+        parent[v] = -1;
+        if (dist[v] == 0) continue;
+        int k = or_neighbours(&g, v, nb);
+        for (int j = 0; j < k; ++j)
+            if (dist[nb[j]] + or_weight(&g, nb[j], v) == dist[v]) {
+                parent[v] = (int32_t)nb[j];
+                if (ORACLE_MUTANT != 1) break;
+            }
+    }
+    return OR_OK;
+}
+
+/* Geodesic centroid and decreasing list of geodesic extrema (Section 3.3):
+ * a propagation from all border pixels, c = first pixel of maximal distance,
+ * a propagation from c, rank[x] = position of x when pixels are sorted by
+ * decreasing distance from c (ties: increasing index). */
+static const int64_t *or_sort_key;
+static int or_cmp_rank(const void *a, const void *b) {
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    if (or_sort_key[i] != or_sort_key[j]) return or_sort_key[i] > or_sort_key[j] ? -1 : 1;
+    if (ORACLE_MUTANT == 3) return i > j ? -1 : (i < j ? 1 : 0);
+    return i < j ? -1 : (i > j ? 1 : 0);
+}
+
+int gapd_oracle_extrema(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                        int32_t *centroid, int64_t *d_edge, int64_t *d_c, int32_t *rank) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    int64_t nb = 0;
+    int64_t *seeds = (int64_t *)malloc((size_t)g.N * sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc((size_t)g.N * sizeof(int64_t));
+    if (!seeds || !order) { free(seeds); free(order); return OR_ENOMEM; }
+    for (int64_t p = 0; p < g.N; ++p) {
+        int y = (int)(p / W), x = (int)(p % W);
+        if (y == 0 || (y == H - 1 && ORACLE_MUTANT != 7) || x == 0 || x == W - 1) seeds[nb++] = p;
+    }
+    st = or_dijkstra(&g, seeds, nb, d_edge);
+    if (!st) {
+        int64_t c = 0;
+        for (int64_t p = 1; p < g.N; ++p)
+            if (d_edge[p] > d_edge[c] || (ORACLE_MUTANT == 6 && d_edge[p] == d_edge[c])) c = p;
+        *centroid = (int32_t)c;
+        st = or_dijkstra(&g, &c, 1, d_c);
+    }
+    if (!st) {
+        for (int64_t p = 0; p < g.N; ++p) order[p] = p;
+        or_sort_key = d_c;
+        qsort(order, (size_t)g.N, sizeof(int64_t), or_cmp_rank);
+        for (int64_t r = 0; r < g.N; ++r) rank[order[r]] = (int32_t)r;
+    }
+    free(seeds); free(order);
+    return st;
+}
+
+/* The filling-rate method (Section 3.4, algorithm "filling").
+ *   D          N*N int32 output (every entry written exactly once)
+ *   seq_out    N int32, the source of each propagation (nullable)
+ *   a_out      N int64, filled pairs a after each propagation (nullable;
+ *              Section 2, eq. _a)
+ *   n_prop     number of propagations in the loop (the two setup propagations
+ *              of the centroid and extrema are not included)
+ *   max_steps  stop after this many propagations (<0: no limit); the call then
+ *              returns OR_TRUNCATED and D is only partly written
+ * The filled-pairs matrix D_mrk (Section 2) is kept as one byte per entry and
+ * the per-point filling rate tau(x) (eq. filling_rate_pt) as the integer
+ * numerator count[x] = sum_k D_mrk(k, x).  */
+int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                             int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
+                             int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    if (!D || !n_prop) return OR_EINVAL;
+    const int64_t N = g.N;
+    uint8_t *mrk = (uint8_t *)calloc((size_t)(N * N), 1);
+    int64_t *count = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int32_t *rank = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    int32_t *parent = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    int64_t *da = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int64_t *db = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    if (!mrk || !count || !rank || !parent || !da || !db) { st = OR_ENOMEM; goto done; }
+
+    /* Compute the decreasing list of geodesic extrema (Section 3.3). */
+    int32_t c;
+    st = gapd_oracle_extrema(img, H, W, C, conn, wmode, &c, da, db, rank);
+    if (st) goto done;
+    if (centroid_out) *centroid_out = c;
+    if (rank_out) memcpy(rank_out, rank, (size_t)N * sizeof(int32_t));
+
+    /* D_mrk(i,i) = 1 by convention, so every point starts with one filled entry. */
+    for (int64_t i = 0; i < N; ++i) { mrk[i * N + i] = 1; count[i] = 1; D[i * N + i] = 0; }
+    int64_t filled = 0, t = 0;
+    *n_prop = 0;
+    for (;;) {
+        /* B = argmin tau; among several, the greatest extremum (smallest rank). */
+        int64_t s = 0;
+        for (int64_t x = 1; x < N; ++x)
+            if (count[x] < count[s] || (count[x] == count[s] && ORACLE_MUTANT != 5 && rank[x] < rank[s])) s = x;
+        if (count[s] == N) break; /* the least filled point is filled: D is filled */
+        if (max_steps >= 0 && t >= max_steps) { st = OR_TRUNCATED; break; }
+
+        /* Compute the geodesic tree from s. */
+        st = or_dijkstra(&g, &s, 1, da);
+        if (st) goto done;
+        gapd_oracle_parents(img, H, W, C, conn, wmode, da, parent);
+
+        /* Fill D along the tree (Property 1): each ancestor u of v gives
+         * d(u,v) = d(s,v) - d(s,u). */
+        for (int64_t v = 0; v < N; ++v) {
+            for (int64_t u = parent[v]; u >= 0; u = parent[u]) {
+                if (mrk[u * N + v]) continue;
+                int64_t duv = da[v] - da[u];
+                if (duv > INT32_MAX) { st = OR_ERANGE; goto done; }
+                D[u * N + v] = (int32_t)duv;
+                if (ORACLE_MUTANT != 4) D[v * N + u] = (int32_t)duv;
+                mrk[u * N + v] = 1;
+                mrk[v * N + u] = 1;
+                count[u] += 1;
+                count[v] += 1;
+                filled += 1;
+            }
+        }
+        if (seq_out) seq_out[t] = (int32_t)s;
+        if (a_out) a_out[t] = filled;
+        ++t;
+        *n_prop = t;
+    }
+done:
+    free(mrk); free(count); free(rank); free(parent); free(da); free(db);
+    return st;
+}
