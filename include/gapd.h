@@ -1,0 +1,205 @@
+/*
+ * gapd.h -- all pairs of geodesic distances on a pixel grid, MI355X (gfx950).
+ *
+ * C ABI of libgapd.so.  The library computes, on the GPU, the N x N array of
+ * geodesic distances between the N = H*W pixels of an image (Noyel, Angulo,
+ * Jeulin, "Fast computation of all pairs of geodesic distances"), either by
+ * the naive method (one geodesic propagation per pixel, Section 1) or by the
+ * filling-rate method (Section 3.4, algorithm "filling"), which propagates
+ * from one source at a time, fills the distances array along each
+ * propagation's geodesic tree (Section 2, Property 1) and picks the next
+ * source as the least filled point, ties broken by the geodesic-extrema list
+ * of Section 3.3.
+ *
+ * Conventions shared by every entry point
+ *   - pixel index i = y*W + x; images are HWC row-major uint8 (C bands);
+ *   - the graph is the 4- or 8-neighbour grid without wrap-around
+ *     (Section 2, eqs. voisinage_1/2); diagonal edges carry the plain
+ *     pseudo-metric (no Euclidean factor);
+ *   - edge weights are integers >= 1: GAPD_W_SUM is d_+(p,q) = f(p) + f(q)
+ *     (Section 2, eq. distance_somme; one band, grey levels should be >= 1
+ *     so that no edge weighs 0); GAPD_W_1PL1 is 1 + sum_b |f_b(p) - f_b(q)|
+ *     for C >= 1 bands (the multiband pseudo-metric Section 5 leaves open);
+ *   - distances are int32; D[i*N + j] is the geodesic distance (Section 2,
+ *     eq. distance) between pixels i and j; D is symmetric with zero diagonal;
+ *   - the geodesic tree of a propagation gives each pixel v != source the
+ *     smallest-index neighbour q with d(q) + w(q,v) == d(v) as parent;
+ *   - device pointers are HIP device addresses (e.g. torch tensor data
+ *     pointers on a ROCm build); host pointers are ordinary process memory;
+ *   - every call returns a status; nothing throws across the ABI.  A device
+ *     error makes the context unusable (later calls return GAPD_EDEVICE).
+ *
+ * Limits: 1 <= H, W <= 512; the largest possible distance, hops * w_max with
+ * hops = H+W-2 (4-neighbours) or max(H,W)-1 (8-neighbours), must be < 2^28,
+ * else GAPD_ERANGE.
+ *
+ * Threading: a context belongs to one host thread and one stream at a time.
+ * A server is safe to call from several host threads.
+ */
+#ifndef GAPD_H
+#define GAPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+#define GAPD_OK        0
+#define GAPD_PENDING   1   /* serving: job admitted or queued, not finished yet          */
+#define GAPD_EINVAL   (-1) /* bad argument (sizes, modes, null pointers, sources range)   */
+#define GAPD_ENOMEM   (-2) /* workspace / arena / budget too small                        */
+#define GAPD_EDEVICE  (-3) /* HIP runtime or kernel error; the context is poisoned        */
+#define GAPD_ERANGE   (-4) /* a distance could reach 2^28                                 */
+#define GAPD_ENOCONV  (-5) /* a propagation hit its sweep-round cap                       */
+#define GAPD_EBUSY    (-6) /* serving: the job is still running                           */
+#define GAPD_ENOTFOUND (-7) /* serving: unknown or released ticket                        */
+
+/* ---- options ----------------------------------------------------------------------------- */
+#define GAPD_CONN4 4
+#define GAPD_CONN8 8
+#define GAPD_W_SUM  0
+#define GAPD_W_1PL1 1
+#define GAPD_MODE_NAIVE        0   /* N propagations, one row of D each (Section 1)          */
+#define GAPD_MODE_TREE_FILL_FR 1   /* filling-rate method (Section 3.4, algorithm filling)  */
+
+typedef struct gapd_ctx gapd_ctx;
+typedef struct gapd_server gapd_server;
+
+/* Statistics of one all-pairs call.  sources_out and filled_out are inputs:
+ * optional DEVICE buffers of N elements each that receive, for the
+ * filling-rate mode, the source of every propagation in order and a(t), the
+ * number of filled pairs after each propagation (Section 2, eq. _a).  All
+ * other fields are outputs. */
+typedef struct {
+    int64_t  n_prop;        /* propagations of the main loop (N for naive)                */
+    int64_t  n_prop_setup;  /* 2 for the filling-rate mode (centroid and extrema), else 0  */
+    int64_t  rounds;        /* sweep rounds summed over all propagations                  */
+    int32_t  centroid;      /* geodesic centroid (filling-rate mode), else -1             */
+    int32_t  _pad;
+    int32_t *sources_out;   /* nullable device buffer, N int32 (input)                     */
+    int64_t *filled_out;    /* nullable device buffer, N int64 (input)                     */
+    float    ms_total;      /* wall time of the call, stream-event timed                   */
+    float    ms_setup;      /* centroid and extrema propagations (filling-rate mode)       */
+} gapd_stats;
+
+/* ---- single image ------------------------------------------------------------------------ */
+
+/* Create a context for one image (Section 2: the image as a grid graph with a
+ * pseudo-metric).  image: HOST pointer to H*W*C bytes, HWC row-major; it is
+ * copied to the device together with the edge weights derived from it, in
+ * device memory the context owns until gapd_destroy.  conn: GAPD_CONN4 or
+ * GAPD_CONN8.  weight_mode: GAPD_W_SUM (requires C == 1) or GAPD_W_1PL1.
+ * Runs on the null stream until gapd_set_stream.  On error *out is NULL. */
+int gapd_create(const uint8_t *image, int H, int W, int C, int conn, int weight_mode, gapd_ctx **out);
+
+/* Use this HIP stream (a hipStream_t passed as void*) for later calls. */
+int gapd_set_stream(gapd_ctx *ctx, void *hip_stream);
+
+/* Bytes of caller-provided device workspace that gapd_all_pairs(mode) needs
+ * (0 for the naive mode).  The filling-rate workspace holds the filled-pairs
+ * bit matrix D_mrk (Section 2), N*ceil(N/32)*4 bytes, plus O(N) arrays. */
+int gapd_workspace_size(gapd_ctx *ctx, int mode, size_t *bytes);
+
+/* Hand the context a DEVICE workspace of at least gapd_workspace_size bytes,
+ * 256-byte aligned.  The caller owns it and must keep it alive while calls
+ * that use it may run on the stream. */
+int gapd_set_workspace(gapd_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* One geodesic propagation per source (Section 1): out[k*N + v] = d(sources[k], v).
+ * sources: DEVICE pointer to K int32 pixel ids in [0, N) (checked on the host
+ * after a copy; out-of-range ids give GAPD_EINVAL and nothing is written);
+ * out: DEVICE pointer to K*N int32.  Asynchronous on the context's stream
+ * apart from the small source-id check. */
+int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out);
+
+/* Every entry of the N x N distances array D.  out: DEVICE pointer to N*N
+ * int32.  mode GAPD_MODE_NAIVE runs N propagations; GAPD_MODE_TREE_FILL_FR
+ * runs the filling-rate method and needs the workspace.  Both give the same,
+ * unique D.  st: nullable host struct.  Returns when the result is complete
+ * on the stream (the call synchronises the stream). */
+int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
+
+/* Release the context and its device memory (not the caller's buffers). */
+void gapd_destroy(gapd_ctx *ctx);
+
+/* Text for a status code, and the context's last error message. */
+const char *gapd_strerror(int status);
+const char *gapd_last_error(gapd_ctx *ctx);
+
+/* ---- many images in one launch ------------------------------------------------------------ */
+
+/* Workspace bytes for gapd_all_pairs_batched with these image sizes (host
+ * arrays H[B], W[B]). */
+int gapd_batched_workspace_size(const int32_t *H, const int32_t *W, int B, int C, int conn, int mode,
+                                size_t *bytes);
+
+/* All-pairs distances of B images in one pass: naive mode runs every
+ * (image, source) propagation of the batch in one kernel launch; the
+ * filling-rate mode runs one persistent workgroup per image, each owning its
+ * image's sequential loop.
+ *   images_packed: HOST, the B images back to back (H[b]*W[b]*C bytes each);
+ *   H, W:          HOST, B sizes each;
+ *   out:           DEVICE int32; image b's N_b x N_b array starts at
+ *                  out + out_offsets[b];
+ *   out_offsets:   HOST, B+1 int64 element offsets (nondecreasing, the span
+ *                  of image b at least N_b^2 elements);
+ *   n_prop_out:    nullable HOST, B int64: loop propagations per image;
+ *   workspace:     DEVICE, gapd_batched_workspace_size bytes, 256-aligned.
+ * Synchronises the stream before returning. */
+int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const int32_t *W, int B, int C,
+                           int conn, int weight_mode, int mode, int32_t *out, const int64_t *out_offsets,
+                           int64_t *n_prop_out, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ---- serving ---------------------------------------------------------------------------------- */
+
+#define GAPD_JOB_ALL_PAIRS    0
+#define GAPD_JOB_MULTI_SOURCE 1
+
+typedef struct {
+    int            kind;        /* GAPD_JOB_ALL_PAIRS or GAPD_JOB_MULTI_SOURCE              */
+    int            H, W, C, conn, weight_mode;
+    int            mode;        /* all-pairs jobs: GAPD_MODE_*                              */
+    const uint8_t *image;       /* HOST, H*W*C bytes; copied at submit                      */
+    const int32_t *sources;     /* HOST, K ids (multi-source jobs); copied at submit        */
+    int            K;
+} gapd_job;
+
+typedef struct {
+    int32_t *dev_out;           /* DEVICE result inside the arena: N*N or K*N int32          */
+    size_t   elems;
+    int64_t  n_prop;            /* all-pairs filling-rate jobs: loop propagations           */
+    double   t_submit, t_admit, t_done;  /* seconds, steady clock of the server           */
+} gapd_result;
+
+/* Create a server over a caller-owned DEVICE arena (arena_bytes, 256-aligned).
+ * Jobs are admitted first come first served while their bytes fit in the arena
+ * and a slot is free (max_slots running jobs); admitted jobs run concurrently
+ * on max_slots streams of the current device.  The server owns a scheduler
+ * thread until gapd_server_destroy. */
+int gapd_server_create(void *arena_dev, size_t arena_bytes, int max_slots, gapd_server **out);
+
+/* Queue a job; never blocks.  The image and sources are copied.  *ticket
+ * identifies it.  GAPD_ENOMEM if the job alone can never fit in the arena. */
+int gapd_serve_submit(gapd_server *srv, const gapd_job *job, uint64_t *ticket);
+
+/* GAPD_PENDING while queued or running, GAPD_OK with *res filled when done
+ * (the result stays valid until gapd_serve_release), or the job's error. */
+int gapd_serve_poll(gapd_server *srv, uint64_t ticket, gapd_result *res);
+
+/* Block until the job is done (or failed); same results as gapd_serve_poll. */
+int gapd_serve_wait(gapd_server *srv, uint64_t ticket, gapd_result *res);
+
+/* Return a finished job's arena bytes so queued jobs can be admitted.
+ * GAPD_EBUSY if it is still running. */
+int gapd_serve_release(gapd_server *srv, uint64_t ticket);
+
+/* Stop the scheduler (waits for running jobs) and free the server. */
+void gapd_server_destroy(gapd_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAPD_H */

@@ -1,0 +1,25 @@
+// Host-side helpers shared by the C ABI (capi.cpp) and the server (server.cpp).
+#pragma once
+
+#include <string>
+
+#include "gapd_internal.h"
+
+namespace gapd {
+
+extern thread_local std::string g_create_error;
+
+int env_int(const char *name, int dflt);
+int validate_image(const uint8_t *img, int H, int W, int C, int conn, int wmode, std::string &why);
+int max_rounds_for(int N);
+
+// Propagations from K sources into K rows of out; synchronises the stream.
+int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
+             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr);
+
+// The filling-rate method on one image (workspace fs, output fs.D); the
+// final control block is copied to hc.  Synchronises the stream.
+int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
+                     FrCtl &hc, std::string &err, bool &poisoned);
+
+}  // namespace gapd

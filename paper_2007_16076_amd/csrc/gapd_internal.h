@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libgapd.so.  Not part of the public ABI (that is include/gapd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace gapd {
+
+// Distances of unreached pixels.  Every real distance is < 2^28 (checked at
+// context creation), so INF + any prefix of edge weights stays below 2^31.
+constexpr int kInf = 0x3FFFFFFF;
+constexpr int kDistLimit = 1 << 28;
+// Direction code of the geodesic-tree root in the packed (d << 4 | code) words.
+constexpr uint32_t kRootCode = 15u;
+constexpr int kRelaxThreads = 256;   // four waves: one per sweep direction
+constexpr int kMaxLine = 512;        // longest image side supported
+
+// Edge weights of one image, all arrays H*W, row-major.  The four weight
+// arrays hold the edge from pixel (y,x) to (y,x+1) [wr], (y+1,x) [wd],
+// (y+1,x+1) [wdr] and (y+1,x-1) [wdl]; entries for edges leaving the image
+// are 0 and never read.  P is the running sum of wr along each row
+// (P[y][x] = sum_{k<x} wr[y][k]).  The c* arrays are the same data for the
+// transposed image (W*H, "column view"): column sweeps are row sweeps of it.
+struct GImg {
+    int H, W, N, conn;
+    const uint16_t *wr, *wd, *wdr, *wdl;
+    const int32_t *P;
+    const uint16_t *cwv, *cwdr, *cwdl;
+    const int32_t *cP;
+};
+
+// Writable twin used only while building the arrays.
+struct GImgW {
+    int H, W, N, conn;
+    uint16_t *wr, *wd, *wdr, *wdl;
+    int32_t *P;
+    uint16_t *cwv, *cwdr, *cwdl;
+    int32_t *cP;
+};
+
+// Bytes of the weight block of an H x W image (256-aligned sub-arrays).
+size_t weight_block_bytes(int H, int W);
+// Lay the weight arrays out in a device block of weight_block_bytes().
+GImgW weight_block_layout(void *dev, int H, int W, int conn);
+inline GImg as_const(const GImgW &w) {
+    GImg g;
+    g.H = w.H; g.W = w.W; g.N = w.N; g.conn = w.conn;
+    g.wr = w.wr; g.wd = w.wd; g.wdr = w.wdr; g.wdl = w.wdl; g.P = w.P;
+    g.cwv = w.cwv; g.cwdr = w.cwdr; g.cwdl = w.cwdl; g.cP = w.cP;
+    return g;
+}
+
+// Device control block of one filling-rate run.
+struct FrCtl {
+    int32_t s;          // source of the current step
+    int32_t done;       // 1 once the least filled point is filled
+    int32_t centroid;
+    int32_t err;        // GAPD_ENOCONV etc. from device code
+    int64_t n_prop;     // propagations done by the main loop
+    int64_t filled;     // a: filled unordered pairs
+    int64_t rounds;     // sweep rounds summed over propagations
+    int64_t pad[3];
+};
+
+// Device state of the filling-rate method for one image.
+struct FrState {
+    int N, MW;                 // pixels; 32-bit words per row of the filled-pairs matrix
+    uint32_t *mask;            // N * MW bits: D_mrk
+    int32_t *count;            // N: filled entries of each row (diagonal included)
+    int32_t *rank;             // N: position in the decreasing geodesic-extrema list
+    int32_t *order;            // N: inverse of rank
+    uint32_t *packed;          // N: (d << 4) | parent direction of the current tree
+    int32_t *dbuf;             // N: distances of the setup propagations
+    int32_t *D;                // N * N output
+    FrCtl *ctl;
+    int32_t *seq_out;          // nullable, N
+    int64_t *filled_out;       // nullable, N
+};
+
+// Workspace layout of a single-image filling-rate run.
+size_t fr_workspace_bytes(int N);
+FrState fr_workspace_layout(void *ws, int N);
+
+// One image of a batch, as the batched kernels see it.
+struct BImg {
+    GImg g;
+    int Wp;             // LDS row stride of the distance tile
+    int _pad;
+    int64_t out_off;    // element offset of the image's N*N block in the output
+    int64_t item0;      // first global work item of the image (naive batched)
+    FrState fr;         // filling-rate state (batched filling-rate mode)
+};
+
+// ---- launchers (defined in kernels.hip) -------------------------------------------------
+struct LaunchStatus {
+    hipError_t err;
+};
+
+// Build weights of one image from its HWC bytes on the device.
+hipError_t launch_prep(const GImgW &w, const uint8_t *img_dev, int C, int wmode, hipStream_t st);
+// Weights of B images at once: descriptors on the device (GImgW[B]), image offsets.
+hipError_t launch_prep_batched(const GImgW *w_dev, const uint8_t *imgs_dev, const int64_t *img_off_dev,
+                               int B, int C, int wmode, hipStream_t st);
+
+// Propagations from sources (list or src_base + block) into K rows of out.
+hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
+                             int max_rounds, FrCtl *ctl, hipStream_t st);
+
+// Filling-rate method pieces for one image.
+hipError_t launch_fr_init(const FrState &fs, hipStream_t st);
+hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
+hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
+
+// Batched naive: every (image, source) item in one launch.
+hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line,
+                                     size_t lds_bytes, int conn, int32_t *out, int max_rounds, FrCtl *ctl,
+                                     hipStream_t st);
+// Batched filling rate: one persistent workgroup per image.
+hipError_t launch_fr_batched(const BImg *imgs_dev, int B, int max_line, size_t lds_bytes, int conn,
+                             int max_rounds, hipStream_t st);
+
+// LDS row stride for an image of width W (odd, so column walks avoid bank conflicts).
+inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }
+// Largest dynamic LDS a workgroup may use.
+constexpr size_t kMaxLds = 160 * 1024 - 1024;
+
+}  // namespace gapd
