@@ -1,0 +1,333 @@
+#!/usr/bin/env python3
+"""Benchmark: all pairs of geodesic distances on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Workloads (synthetic inputs from ``synth``; the paper's own images are not
+available):
+  blob128    (default) 128x128 blob image, 4-neighbours, w = f(p)+f(q):
+             a step is one all-pairs call of the filling-rate method
+             (Section 3.4), 16384^2 int32 = 1 GiB; the naive method (one
+             propagation per pixel) is timed beside it on the same image
+  uniform32  32x32 iid image, naive method (4 MiB output)
+  voronoi192 192x192x8 Voronoi image, w = 1 + L1, filling-rate vs naive (5.4 GB)
+  batched    256 iid images of sides 24..96 in one call, both methods
+  serve      Poisson request stream through the continuous-batching server
+
+Prints ONE JSON line.  Inputs are resident on the GPU when the timed region
+starts; the timed region is bracketed by torch.cuda.synchronize().
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "distance entries/sec and HBM GB/s fraction, tree_fill vs naive GPU; p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E, published
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 int32 lanes/clk x 2.4 GHz = 39.3 Tops/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on a bounded sample of the same workload.
+# ---------------------------------------------------------------------------------------------
+def cpu_baseline_fr(img, conn, n_prop_total, budget_s):
+    import oracle
+    N = img.shape[0] * img.shape[1]
+    t0 = time.perf_counter()
+    oracle.extrema(img, conn=conn)
+    t_setup = time.perf_counter() - t0
+    probe = 8
+    t0 = time.perf_counter()
+    oracle.filling_rate(img, conn=conn, max_steps=probe)
+    t_probe = time.perf_counter() - t0
+    per = max((t_probe - t_setup) / probe, 1e-6)
+    steps = int(max(probe, min(n_prop_total, (budget_s - t_setup) / per)))
+    t0 = time.perf_counter()
+    fr = oracle.filling_rate(img, conn=conn, max_steps=steps)
+    t = time.perf_counter() - t0
+    per = (t - t_setup) / max(fr.n_prop, 1)
+    t_total = t_setup + per * n_prop_total
+    return {"value": N * N / t_total, "unit": "distance entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {fr.n_prop} of {n_prop_total} filling-rate steps (the loop is sequential; 1 thread); "
+                      f"whole-job time extrapolated as setup + {n_prop_total} x mean step time",
+            "seconds_measured": round(t, 2), "seconds_extrapolated": round(t_total, 1)}
+
+
+def cpu_baseline_naive(img, conn, budget_s):
+    import oracle
+    N = img.shape[0] * img.shape[1]
+    cores = host_cores()
+    rows = min(N, max(cores, 64))
+    t0 = time.perf_counter()
+    oracle.rows(img, np.arange(rows), conn=conn, threads=cores)
+    t = time.perf_counter() - t0
+    rows2 = int(min(N, max(rows, rows * budget_s / max(t, 1e-6))))
+    if rows2 > rows:
+        t0 = time.perf_counter()
+        oracle.rows(img, np.arange(rows2), conn=conn, threads=cores)
+        t = time.perf_counter() - t0
+        rows = rows2
+    return {"value": rows * N / t, "unit": "distance entries/s", "cores": cores, "kind": "oracle",
+            "sample": f"naive method, propagations from the first {rows} of {N} sources, OpenMP over sources"}
+
+
+# ---------------------------------------------------------------------------------------------
+# Single-image workloads: filling rate vs naive.
+# ---------------------------------------------------------------------------------------------
+def run_single(args, name, img, conn, modes):
+    import torch
+    from paper_2007_16076_amd import gapd
+    ctx = gapd.Context(img, conn=conn)
+    N = ctx.N
+    out = torch.empty((N, N), dtype=torch.int32, device="cuda")
+    res = {}
+    for mode in modes:
+        stats, wall = [], []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = ctx.all_pairs(mode, out=out, time_kernels=(mode == gapd.MODE_TREE_FILL_FR))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
+            log(f"[{name}] mode={mode} call {i}: {dt:.1f} ms (events {st.ms_total:.1f} ms) n_prop={st.n_prop}")
+            if i >= args.warmup:
+                stats.append(st)
+                wall.append(dt)
+        res[mode] = (stats, wall)
+    return ctx, res
+
+
+def roofline_hbm(bytes_per_launch, ms):
+    ach = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None}
+
+
+def single_image_line(args, workload, img, conn, desc, fr=True):
+    from paper_2007_16076_amd import gapd
+    N = img.shape[0] * img.shape[1]
+    E_dir = edges_directed(img.shape[0], img.shape[1], conn)
+    modes = [gapd.MODE_TREE_FILL_FR, gapd.MODE_NAIVE] if fr else [gapd.MODE_NAIVE]
+    ctx, res = run_single(args, workload, img, conn, modes)
+    nst, nwall = res[gapd.MODE_NAIVE]
+    naive_ms = [s.ms_total for s in nst]
+    naive_kernel_ms = float(np.mean([s.ms_kernel for s in nst]))
+    naive_rounds = float(np.mean([s.rounds for s in nst])) / N
+    naive = {"value": N * N / (np.mean(naive_ms) * 1e-3), "unit": "distance entries/s",
+             "ms_per_call": round(float(np.mean(naive_ms)), 3), "p50_ms": round(pct(naive_ms, 50), 3),
+             "p99_ms": round(pct(naive_ms, 99), 3), "kernel_ms": round(naive_kernel_ms, 3),
+             "rounds_per_propagation": round(naive_rounds, 2)}
+    roof_naive = roofline_hbm(4.0 * N * N, naive_kernel_ms)
+    roof_naive["kernel"] = "k_relax_rows (one propagation per workgroup, writes its row of D)"
+    roof_naive["algorithmic_bytes_per_launch"] = 4 * N * N
+    line = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic", "config": dict(desc, workload=workload, N=N, conn=conn,
+                                                output_bytes=4 * N * N)}
+    if not fr:
+        line.update(value=naive["value"], unit="distance entries/s", ms_per_step=naive["ms_per_call"],
+                    p50_ms=naive["p50_ms"], p99_ms=naive["p99_ms"], naive=naive, roofline=roof_naive)
+        line["config"]["mode"] = "naive"
+        return line, ctx
+    fst, fwall = res[gapd.MODE_TREE_FILL_FR]
+    fr_ms = [s.ms_total for s in fst]
+    s0 = fst[-1]
+    n_prop = s0.n_prop
+    step_ms = float(np.mean([s.ms_step_kernels for s in fst])) / max(n_prop, 1)
+    fill_ms = float(np.mean([s.ms_fill_kernels for s in fst])) / max(n_prop, 1)
+    rounds = s0.rounds / max(n_prop + 2, 1)
+    # Per-launch algorithmic work (units stated in the design doc):
+    #   fill: the D entries and mask bits the whole run writes once, averaged per launch;
+    #   step: |E_dir| x rounds relaxations (add + min) of one propagation.
+    fill_bytes = (4.0 * N * N + N * N / 8.0) / max(n_prop, 1)
+    roof_fill = roofline_hbm(fill_bytes, fill_ms)
+    roof_fill.update(kernel="k_fr_fill (redundancy fill along the geodesic tree)",
+                     algorithmic_bytes_per_launch=round(fill_bytes), avg_launch_ms=round(fill_ms, 5))
+    step_ops = 2.0 * E_dir * rounds
+    ach = step_ops / (step_ms * 1e-3) / 1e12
+    roof_step = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
+                 "frac": round(ach / VALU_PEAK_TOPS, 6), "traffic": None,
+                 "kernel": "k_fr_step (least-filled select + one propagation + tree, one workgroup)",
+                 "algorithmic_ops_per_launch": round(step_ops), "avg_launch_ms": round(step_ms, 5)}
+    dominant, other = (roof_step, roof_fill) if step_ms >= fill_ms else (roof_fill, roof_step)
+    value = N * N / (np.mean(fr_ms) * 1e-3)
+    line.update(value=value, unit="distance entries/s", ms_per_step=round(float(np.mean(fr_ms)), 3),
+                p50_ms=round(pct(fr_ms, 50), 3), p99_ms=round(pct(fr_ms, 99), 3),
+                n_prop=int(n_prop), n_prop_setup=int(s0.n_prop_setup),
+                propagation_saving_vs_naive=round(1.0 - (n_prop + s0.n_prop_setup) / N, 4),
+                fr_setup_ms=round(float(np.mean([s.ms_setup for s in fst])), 3),
+                fr_loop_kernel_ms={"select_propagate": round(step_ms * n_prop, 3),
+                                   "fill": round(fill_ms * n_prop, 3)},
+                naive=naive, fr_time_over_naive=round(float(np.mean(fr_ms)) / naive["ms_per_call"], 2),
+                roofline=dominant, roofline_other=other, roofline_naive=roof_naive)
+    line["config"]["mode"] = "tree_fill_filling_rate (naive timed beside it)"
+    return line, ctx
+
+
+def edges_directed(H, W, conn):
+    e = H * (W - 1) + (H - 1) * W
+    if conn == 8:
+        e += 2 * (H - 1) * (W - 1)
+    return 2 * e
+
+
+# ---------------------------------------------------------------------------------------------
+# Batched and serving workloads.
+# ---------------------------------------------------------------------------------------------
+def batched_line(args):
+    import torch
+    import synth
+    from paper_2007_16076_amd import gapd
+    imgs = synth.config4()
+    shapes = [im.shape for im in imgs]
+    offs = gapd.pack_offsets(shapes)
+    total = int(offs[-1])
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    res = {}
+    for mode in (gapd.MODE_NAIVE, gapd.MODE_TREE_FILL_FR):
+        ws = torch.empty(gapd.batched_workspace_size(shapes, mode=mode), dtype=torch.uint8, device="cuda")
+        ms = []
+        steps = args.steps if mode == gapd.MODE_NAIVE else max(1, min(args.steps, 2))
+        for i in range(args.warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, nprop = gapd.all_pairs_batched(imgs, mode=mode, out=out, offsets=offs, workspace=ws)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
+            log(f"[batched] mode={mode} call {i}: {dt:.1f} ms")
+            if i >= args.warmup:
+                ms.append(dt)
+        res[mode] = (ms, nprop)
+    nms, _ = res[gapd.MODE_NAIVE]
+    fms, fprop = res[gapd.MODE_TREE_FILL_FR]
+    n_sum = sum(h * w for h, w in shapes)
+    line = {"metric": METRIC, "value": total / (np.mean(fms) * 1e-3), "unit": "distance entries/s",
+            "n_gpus": 1, "steps": len(fms), "warmup": args.warmup, "ms_per_step": round(float(np.mean(fms)), 2),
+            "p50_ms": round(pct(fms, 50), 2), "p99_ms": round(pct(fms, 99), 2),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": "batched256", "images": len(imgs), "sides": "24..96", "conn": 4,
+                       "entries": total, "output_bytes": 4 * total, "mode": "tree_fill_filling_rate"},
+            "naive": {"value": total / (np.mean(nms) * 1e-3), "ms_per_call": round(float(np.mean(nms)), 2),
+                      "p50_ms": round(pct(nms, 50), 2), "p99_ms": round(pct(nms, 99), 2),
+                      "hbm_gbps_output": round(4 * total / (np.mean(nms) * 1e-3) / 1e9, 1)},
+            "propagation_saving_vs_naive": round(1.0 - (float(np.sum(fprop)) + 2 * len(imgs)) / n_sum, 4),
+            "roofline": roofline_hbm(4.0 * total, float(np.mean(nms)))}
+    line["roofline"]["kernel"] = "k_relax_rows_batched (whole naive call, output bytes only)"
+    return line
+
+
+def serve_line(args):
+    import torch
+    import synth
+    from paper_2007_16076_amd import gapd
+    rate, n = args.rate, args.requests
+    reqs, images = synth.serving_trace(rate, n, side=(64, 192))
+    free, _ = torch.cuda.mem_get_info()
+    arena_bytes = int(min(200e9, free * 0.8))
+    srv = gapd.Server(arena_bytes, max_slots=args.slots)
+    mode = gapd.MODE_TREE_FILL_FR if args.serve_mode == "tree_fill" else gapd.MODE_NAIVE
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        while time.perf_counter() - t0 < r.t_arrival:
+            time.sleep(min(0.001, r.t_arrival - (time.perf_counter() - t0)))
+        if r.kind == "all_pairs":
+            t = srv.submit_all_pairs(images[r.image_id], mode=mode)
+        else:
+            t = srv.submit_multi_source(images[r.image_id], r.sources)
+        tickets.append((t, r))
+    lat, entries, done = [], 0, 0
+    for t, r in tickets:
+        res = srv.wait(t)
+        lat.append((res.t_done - res.t_submit) * 1e3)
+        entries += res.elems
+        srv.release(t)
+        done += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    srv.close()
+    return {"metric": METRIC, "value": entries / wall, "unit": "distance entries/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1), "p50_ms": round(pct(lat, 50), 2),
+            "p99_ms": round(pct(lat, 99), 2), "jobs_per_s": round(n / wall, 2), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "serve", "rate_req_s": rate, "requests": n, "slots": args.slots,
+                       "all_pairs_mode": args.serve_mode, "arena_bytes": arena_bytes}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="blob128",
+                    choices=["blob128", "uniform32", "voronoi192", "batched", "serve"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle timing sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=30.0)
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serve-mode", default="naive", choices=["naive", "tree_fill"])
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
+                                   "DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import synth
+    if args.workload == "blob128":
+        img = synth.config2()
+        line, _ = single_image_line(args, "blob128", img, 4,
+                                    {"image": "128x128 sum of 20 Gaussian blobs + noise, seed 1",
+                                     "weights": "f(p)+f(q)", "sha256": synth.sha256(img)})
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_fr(img, 4, line["n_prop"], args.cpu_seconds)
+            line["cpu_baseline_naive"] = cpu_baseline_naive(img, 4, args.cpu_seconds / 3)
+    elif args.workload == "uniform32":
+        img = synth.config1()
+        line, _ = single_image_line(args, "uniform32", img, 4, {"image": "32x32 iid uniform [1,255], seed 0",
+                                                                "weights": "f(p)+f(q)"}, fr=False)
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_naive(img, 4, args.cpu_seconds)
+    elif args.workload == "voronoi192":
+        img = synth.config3()
+        line, _ = single_image_line(args, "voronoi192", img, 4,
+                                    {"image": "192x192x8 Voronoi, 50 regions, noise sigma 6, seed 2",
+                                     "weights": "1 + L1 over 8 bands"})
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_fr(img, 4, line["n_prop"], args.cpu_seconds)
+    elif args.workload == "batched":
+        line = batched_line(args)
+    else:
+        line = serve_line(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

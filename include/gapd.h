@@ -30,7 +30,7 @@
  *     error makes the context unusable (later calls return GAPD_EDEVICE).
  *
  * Limits: 1 <= H, W <= 512; the largest possible distance, hops * w_max with
- * hops = H+W-2 (4-neighbours) or max(H,W)-1 (8-neighbours), must be < 2^28,
+ * hops = H+W-2 (4-neighbours) or max(H,W)-1 (8-neighbours), must be < 2^27,
  * else GAPD_ERANGE.
  *
  * Threading: a context belongs to one host thread and one stream at a time.
@@ -52,7 +52,7 @@ extern "C" {
 #define GAPD_EINVAL   (-1) /* bad argument (sizes, modes, null pointers, sources range)   */
 #define GAPD_ENOMEM   (-2) /* workspace / arena / budget too small                        */
 #define GAPD_EDEVICE  (-3) /* HIP runtime or kernel error; the context is poisoned        */
-#define GAPD_ERANGE   (-4) /* a distance could reach 2^28                                 */
+#define GAPD_ERANGE   (-4) /* a distance could reach 2^27                                 */
 #define GAPD_ENOCONV  (-5) /* a propagation hit its sweep-round cap                       */
 #define GAPD_EBUSY    (-6) /* serving: the job is still running                           */
 #define GAPD_ENOTFOUND (-7) /* serving: unknown or released ticket                        */
@@ -83,6 +83,13 @@ typedef struct {
     int64_t *filled_out;    /* nullable device buffer, N int64 (input)                     */
     float    ms_total;      /* wall time of the call, stream-event timed                   */
     float    ms_setup;      /* centroid and extrema propagations (filling-rate mode)       */
+    float    ms_kernel;     /* naive mode: duration of its single propagation kernel,
+                               timed by events on the context's stream                    */
+    int32_t  time_kernels;  /* input: nonzero asks the filling-rate mode to time each
+                               launch of its two loop kernels with events                 */
+    float    ms_step_kernels; /* sum of durations of the select+propagate launches        */
+    float    ms_fill_kernels; /* sum of durations of the redundancy-fill launches         */
+    int32_t  _pad2;
 } gapd_stats;
 
 /* ---- single image ------------------------------------------------------------------------ */
@@ -111,8 +118,8 @@ int gapd_set_workspace(gapd_ctx *ctx, void *dev_ptr, size_t bytes);
 /* One geodesic propagation per source (Section 1): out[k*N + v] = d(sources[k], v).
  * sources: DEVICE pointer to K int32 pixel ids in [0, N) (checked on the host
  * after a copy; out-of-range ids give GAPD_EINVAL and nothing is written);
- * out: DEVICE pointer to K*N int32.  Asynchronous on the context's stream
- * apart from the small source-id check. */
+ * out: DEVICE pointer to K*N int32.  Returns when the rows are complete (the
+ * call synchronises the context's stream). */
 int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out);
 
 /* Every entry of the N x N distances array D.  out: DEVICE pointer to N*N

@@ -60,7 +60,7 @@ int validate_image(const uint8_t *img, int H, int W, int C, int conn, int wmode,
         }
     if (wmin < 1 && H * W > 1) { why = "an edge weighs 0 (two neighbouring zero pixels under GAPD_W_SUM)"; return GAPD_EINVAL; }
     const int64_t hops = conn == 4 ? (int64_t)H + W - 2 : (int64_t)std::max(H, W) - 1;
-    if (hops * wmax >= kDistLimit) { why = "distances could reach 2^28"; return GAPD_ERANGE; }
+    if (hops * wmax >= kDistLimit) { why = "distances could reach 2^27"; return GAPD_ERANGE; }
     return GAPD_OK;
 }
 
@@ -158,7 +158,7 @@ int gapd_create(const uint8_t *image, int H, int W, int C, int conn, int weight_
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
-        hipFree(c->dev);
+        (void)hipFree(c->dev);
         delete c;
         return GAPD_EDEVICE;
     }
@@ -214,18 +214,19 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
     gapd_stats local{};
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
+    s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0;
     hipEvent_t e0, e1, e2;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
     HIP_OR_FAIL(ctx, hipEventCreate(&e2));
     struct EvGuard {
         hipEvent_t a, b, c;
-        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); hipEventDestroy(c); }
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
     } guard{e0, e1, e2};
     HIP_OR_FAIL(ctx, hipEventRecord(e0, ctx->stream));
     if (mode == GAPD_MODE_NAIVE) {
         st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
-                      ctx->poisoned, &s.rounds);
+                      ctx->poisoned, &s.rounds, &s.ms_kernel);
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = ctx->N;
@@ -237,7 +238,11 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         fs.seq_out = s.sources_out;
         fs.filled_out = s.filled_out;
         FrCtl hc{};
-        st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, e1, hc, ctx->err, ctx->poisoned);
+        float kt[2] = {0.f, 0.f};
+        st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, e1, hc, ctx->err, ctx->poisoned,
+                              s.time_kernels ? kt : nullptr);
+        s.ms_step_kernels = kt[0];
+        s.ms_fill_kernels = kt[1];
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = hc.n_prop;
@@ -255,8 +260,8 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
 void gapd_destroy(gapd_ctx *ctx) {
     if (!ctx) return;
     if (ctx->dev) {
-        hipStreamSynchronize(ctx->stream);
-        hipFree(ctx->dev);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->dev);
     }
     delete ctx;
 }
@@ -266,9 +271,15 @@ void gapd_destroy(gapd_ctx *ctx) {
 namespace gapd {
 
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
-             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out) {
+             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel) {
+    hipEvent_t k0 = nullptr, k1 = nullptr;
+    if (ms_kernel) {
+        if (hipEventCreate(&k0) != hipSuccess || hipEventCreate(&k1) != hipSuccess) ms_kernel = nullptr;
+    }
     hipError_t e = hipMemsetAsync(ctl, 0, sizeof(FrCtl), stream);
+    if (e == hipSuccess && ms_kernel) e = hipEventRecord(k0, stream);
     if (e == hipSuccess) e = launch_relax_rows(g, src_list, src_base, K, out, max_rounds, ctl, stream);
+    if (e == hipSuccess && ms_kernel) e = hipEventRecord(k1, stream);
     FrCtl hc{};
     if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl, sizeof(FrCtl), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -278,12 +289,18 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
         return GAPD_EDEVICE;
     }
     if (rounds_out) *rounds_out = hc.rounds;
+    if (ms_kernel) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, k0, k1) == hipSuccess) *ms_kernel = ms;
+    }
+    if (k0) (void)hipEventDestroy(k0);
+    if (k1) (void)hipEventDestroy(k1);
     if (hc.err) { err = "a propagation hit the sweep-round cap"; return hc.err; }
     return GAPD_OK;
 }
 
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned) {
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt) {
     const int N = g.N;
     auto bad = [&](hipError_t e, const char *where) {
         poisoned = true;
@@ -299,21 +316,44 @@ int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream
     // The loop runs on the device: each step selects its own source, so the
     // host only enqueues steps in chunks and reads the done flag between them.
     const int chunk = std::max(1, env_int("GAPD_FR_CHUNK", 64));
+    std::vector<hipEvent_t> ev;
+    if (kt) {
+        kt[0] = kt[1] = 0.f;
+        ev.resize(3 * (size_t)chunk);
+        for (auto &x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return bad(hipErrorOutOfMemory, "timing events");
+    }
+    struct EvFree {
+        std::vector<hipEvent_t> &v;
+        ~EvFree() { for (auto x : v) (void)hipEventDestroy(x); }
+    } ev_free{ev};
     int64_t enq = 0;
+    int status = GAPD_OK;
     for (;;) {
         for (int i = 0; i < chunk; ++i) {
-            e = launch_fr_step(g, fs, max_rounds, stream);
+            if (kt) (void)hipEventRecord(ev[3 * i], stream);
+            e = launch_fr_step(g, fs, max_rounds, stream, kt ? ev[3 * i + 1] : nullptr);
             if (e != hipSuccess) return bad(e, "filling-rate step");
+            if (kt) (void)hipEventRecord(ev[3 * i + 2], stream);
         }
-        enq += chunk;
         e = hipMemcpyAsync(&hc, fs.ctl, sizeof(FrCtl), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return bad(e, "filling-rate poll");
-        if (hc.err) { err = "a propagation hit the sweep-round cap"; return hc.err; }
+        if (kt) {
+            // Step enq+i did work if it ran before the loop finished.
+            for (int i = 0; i < chunk; ++i) {
+                if (enq + i >= hc.n_prop) break;
+                float a = 0, b = 0;
+                if (hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]) == hipSuccess) kt[0] += a;
+                if (hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]) == hipSuccess) kt[1] += b;
+            }
+        }
+        enq += chunk;
+        if (hc.err) { err = "a propagation hit the sweep-round cap"; status = hc.err; break; }
         if (hc.done) break;
         if (enq > (int64_t)N + 2 * chunk) { err = "filling-rate loop did not terminate"; return GAPD_EDEVICE; }
     }
-    return GAPD_OK;
+    return status;
 }
 
 }  // namespace gapd
@@ -418,7 +458,8 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
         max_line = std::max(max_line, std::max(H[b], W[b]));
         size_t l = (size_t)H[b] * x.Wp * 4;
         if (mode == GAPD_MODE_TREE_FILL_FR) {
-            l = al256(l + (size_t)N);
+            // distances (then tree words) and parent codes
+            l = l + (size_t)((N + 3) / 4) * 4;
             x.fr = fr_workspace_layout(frbase + p.fr_off[b], N);
             x.fr.D = out + out_offsets[b];
         }

@@ -15,11 +15,15 @@ int max_rounds_for(int N);
 
 // Propagations from K sources into K rows of out; synchronises the stream.
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
-             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr);
+             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr,
+             float *ms_kernel = nullptr);
 
 // The filling-rate method on one image (workspace fs, output fs.D); the
 // final control block is copied to hc.  Synchronises the stream.
+// With kt non-null, every loop launch is bracketed by events and the summed
+// durations of the launches that did work are returned in kt[0] (select +
+// propagate) and kt[1] (fill).
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned);
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt = nullptr);
 
 }  // namespace gapd

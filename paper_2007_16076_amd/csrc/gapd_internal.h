@@ -8,10 +8,11 @@
 
 namespace gapd {
 
-// Distances of unreached pixels.  Every real distance is < 2^28 (checked at
-// context creation), so INF + any prefix of edge weights stays below 2^31.
+// Distances of unreached pixels.  Every real distance is < 2^27 (checked at
+// context creation; it leaves room for 5 flag bits in the tree words), so
+// INF + any prefix of edge weights stays below 2^31.
 constexpr int kInf = 0x3FFFFFFF;
-constexpr int kDistLimit = 1 << 28;
+constexpr int kDistLimit = 1 << 27;
 // Direction code of the geodesic-tree root in the packed (d << 4 | code) words.
 constexpr uint32_t kRootCode = 15u;
 constexpr int kRelaxThreads = 256;   // four waves: one per sweep direction
@@ -71,7 +72,7 @@ struct FrState {
     int32_t *count;            // N: filled entries of each row (diagonal included)
     int32_t *rank;             // N: position in the decreasing geodesic-extrema list
     int32_t *order;            // N: inverse of rank
-    uint32_t *packed;          // N: (d << 4) | parent direction of the current tree
+    uint32_t *packed;          // N: tree words (distance, complete-row flag, parent direction)
     int32_t *dbuf;             // N: distances of the setup propagations
     int32_t *D;                // N * N output
     FrCtl *ctl;
@@ -111,7 +112,9 @@ hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_bas
 // Filling-rate method pieces for one image.
 hipError_t launch_fr_init(const FrState &fs, hipStream_t st);
 hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
-hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
+// One loop step: select + propagate + tree (one workgroup), then the fill.
+// If mid is given it is recorded between the two launches.
+hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid = nullptr);
 
 // Batched naive: every (image, source) item in one launch.
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line,

@@ -28,6 +28,15 @@ namespace {
 
 constexpr int kBig = 0x7FFFFFFF;
 
+// Tree word of a pixel for one propagation: bits 0-3 the parent direction
+// code (kRootCode at the root), bit 4 set when the pixel's row of the
+// filled-pairs matrix was already complete before this step, bits 5-31 the
+// distance from the source (< 2^27).
+constexpr uint32_t kFilledBit = 16u;
+__host__ __device__ inline uint32_t tree_word(int d, uint32_t code) { return ((uint32_t)d << 5) | code; }
+__host__ __device__ inline int tw_dist(uint32_t w) { return (int)(w >> 5); }
+__host__ __device__ inline uint32_t tw_code(uint32_t w) { return w & 15u; }
+
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------------------------------
@@ -112,35 +121,55 @@ __device__ __forceinline__ int dpp_mov(int old, int v) {
     return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
 }
 
-// Exclusive prefix minimum: lane l receives min over lanes < l (kBig for lane 0).
-__device__ __forceinline__ int wave_excl_prefix_min(int x, int row) {
-    x = min(x, dpp_mov<0x111>(kBig, x));  // row_shr:1
-    x = min(x, dpp_mov<0x112>(kBig, x));  // row_shr:2
-    x = min(x, dpp_mov<0x114>(kBig, x));  // row_shr:4
-    x = min(x, dpp_mov<0x118>(kBig, x));  // row_shr:8
-    const int t0 = __builtin_amdgcn_readlane(x, 15);
-    const int t1 = __builtin_amdgcn_readlane(x, 31);
-    const int t2 = __builtin_amdgcn_readlane(x, 47);
-    const int c1 = t0, c2 = min(t0, t1), c3 = min(c2, t2);
-    const int carry = row == 0 ? kBig : (row == 1 ? c1 : (row == 2 ? c2 : c3));
-    x = min(x, carry);
-    return dpp_mov<0x111>(carry, x);  // first lane of each row takes the carry
+// Lane masks of the 16-lane DPP row a lane sits in (row = lane / 16), used to
+// pick the carry of the rows before / after it without branching.
+struct RowMasks {
+    int ge1, ge2, ge3, le0, le1, le2;
+    __device__ explicit RowMasks(int row)
+        : ge1(row >= 1 ? -1 : 0), ge2(row >= 2 ? -1 : 0), ge3(row >= 3 ? -1 : 0),
+          le0(row <= 0 ? -1 : 0), le1(row <= 1 ? -1 : 0), le2(row <= 2 ? -1 : 0) {}
+};
+
+__device__ __forceinline__ int sel(int mask, int a, int b) { return (a & mask) | (b & ~mask); }
+
+// Both exclusive scans at once: x = prefix minimum over lanes < l of p,
+// y = suffix minimum over lanes > l of q.  Interleaving the two dependency
+// chains hides most of the DPP and readlane latency.
+__device__ __forceinline__ int2 wave_excl_scans(int p, int q, const RowMasks &m) {
+    p = min(p, dpp_mov<0x111>(kBig, p));
+    q = min(q, dpp_mov<0x101>(kBig, q));
+    p = min(p, dpp_mov<0x112>(kBig, p));
+    q = min(q, dpp_mov<0x102>(kBig, q));
+    p = min(p, dpp_mov<0x114>(kBig, p));
+    q = min(q, dpp_mov<0x104>(kBig, q));
+    p = min(p, dpp_mov<0x118>(kBig, p));
+    q = min(q, dpp_mov<0x108>(kBig, q));
+    const int a0 = __builtin_amdgcn_readlane(p, 15);
+    const int b1 = __builtin_amdgcn_readlane(q, 16);
+    const int a1 = __builtin_amdgcn_readlane(p, 31);
+    const int b2 = __builtin_amdgcn_readlane(q, 32);
+    const int a2 = __builtin_amdgcn_readlane(p, 47);
+    const int b3 = __builtin_amdgcn_readlane(q, 48);
+    int cp = sel(m.ge1, a0, kBig);
+    int cq = sel(m.le0, b1, kBig);
+    cp = min(cp, sel(m.ge2, a1, kBig));
+    cq = min(cq, sel(m.le1, b2, kBig));
+    cp = min(cp, sel(m.ge3, a2, kBig));
+    cq = min(cq, sel(m.le2, b3, kBig));
+    p = min(p, cp);
+    q = min(q, cq);
+    return make_int2(dpp_mov<0x111>(cp, p), dpp_mov<0x101>(cq, q));
 }
 
-// Exclusive suffix minimum: lane l receives min over lanes > l (kBig for lane 63).
-__device__ __forceinline__ int wave_excl_suffix_min(int x, int row) {
-    x = min(x, dpp_mov<0x101>(kBig, x));  // row_shl:1
-    x = min(x, dpp_mov<0x102>(kBig, x));  // row_shl:2
-    x = min(x, dpp_mov<0x104>(kBig, x));  // row_shl:4
-    x = min(x, dpp_mov<0x108>(kBig, x));  // row_shl:8
-    const int t1 = __builtin_amdgcn_readlane(x, 16);
-    const int t2 = __builtin_amdgcn_readlane(x, 32);
-    const int t3 = __builtin_amdgcn_readlane(x, 48);
-    const int c2 = t3, c1 = min(t2, t3), c0 = min(t1, c1);
-    const int carry = row == 3 ? kBig : (row == 2 ? c2 : (row == 1 ? c1 : c0));
-    x = min(x, carry);
-    return dpp_mov<0x101>(carry, x);  // last lane of each row takes the carry
-}
+// Inputs of one line of a sweep, prefetched into registers.
+template <int C>
+struct LineIn {
+    int cur[C];  // distances as read before relaxing the line
+    int P[C];    // running weight sum along the line
+    int wc[C];   // cross edge from the previous line, same element
+    int wm[C];   // 8-neighbours: cross edge from element e-1 of the previous line
+    int wp[C];   // 8-neighbours: cross edge from element e+1 of the previous line
+};
 
 // ---------------------------------------------------------------------------------------------
 // One directional sweep over all lines of a view (rows of the image, or rows
@@ -148,109 +177,114 @@ __device__ __forceinline__ int wave_excl_suffix_min(int x, int row) {
 // the sweep (cross edges), then exactly along itself: with R[e] the running
 // weight sum along the line, min_{e'}(a[e'] + |R[e]-R[e']|) is a prefix
 // minimum of a - R plus R and a suffix minimum of a + R minus R.  A lane owns
-// C consecutive elements.  Writes go through an atomic min, so the four
+// C consecutive elements.  Stores go through an atomic min, so the four
 // sweeps of a round may run concurrently on the same distance field: every
 // stored value is the length of a real path, and values only decrease.
-// Returns true if this wave lowered any value.
+// Line inputs are loaded PF lines ahead into a register ring; all addresses
+// are clamped into the image, so the loads are unconditional.
+// Returns true if this wave lowered a value it had read.
 // ---------------------------------------------------------------------------------------------
 template <int CONN, int C, bool FWD, bool G>
-__device__ bool sweep(int *d, int ls, int es, int NL, int L, const uint16_t *__restrict__ wv,
+__device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, const uint16_t *__restrict__ wv,
                       const uint16_t *__restrict__ wdr, const uint16_t *__restrict__ wdl,
                       const int32_t *__restrict__ P) {
+    constexpr int PF = C <= 4 ? 4 : 2;
     const int lane = __lane_id();
-    const int row = lane >> 4;
+    const RowMasks rm(lane >> 4);
     const int e0 = lane * C;
-    bool changed = false;
-    int prev[C];
+    int ec[C], em[C], ep[C];
+    bool ok[C], okm[C], okp[C];
 #pragma unroll
-    for (int j = 0; j < C; ++j) prev[j] = kInf;
-
-    // Registers holding the next line's inputs (prefetched one line ahead).
-    int ncur[C], nP[C], nwc[C], nwm[C], nwp[C];
-    auto load = [&](int step) {
+    for (int j = 0; j < C; ++j) {
+        const int e = e0 + j;
+        ok[j] = e < L;
+        ec[j] = ok[j] ? e : L - 1;
+        okm[j] = ok[j] && e > 0;
+        okp[j] = e + 1 < L;
+        em[j] = okm[j] ? e - 1 : ec[j];
+        ep[j] = okp[j] ? e + 1 : ec[j];
+    }
+    auto load = [&](LineIn<C> &in, int step) {
         const int l = FWD ? step : NL - 1 - step;
+        const int top = FWD ? (l > 0 ? l - 1 : 0) : l;  // line holding the cross edges into l
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const int e = e0 + j;
-            const bool ok = e < L;
-            ncur[j] = ok ? ldd<G>(&d[l * ls + e * es]) : kInf;
-            nP[j] = P[l * L + (ok ? e : L - 1)];
-            nwc[j] = kInf;
-            nwm[j] = kInf;
-            nwp[j] = kInf;
-            if (step > 0 && ok) {
-                const int top = FWD ? l - 1 : l;
-                nwc[j] = wv[top * L + e];
-                if (CONN == 8) {
-                    if (FWD) {
-                        if (e > 0) nwm[j] = wdr[(l - 1) * L + e - 1];
-                        if (e + 1 < L) nwp[j] = wdl[(l - 1) * L + e + 1];
-                    } else {
-                        if (e > 0) nwm[j] = wdl[l * L + e];
-                        if (e + 1 < L) nwp[j] = wdr[l * L + e];
-                    }
-                }
+            const int v = ldd<G>(&d[l * ls + ec[j] * es]);
+            in.cur[j] = ok[j] ? v : kInf;
+            in.P[j] = P[l * L + ec[j]];
+            in.wc[j] = wv[top * L + ec[j]];
+            if (CONN == 8) {
+                const int a = FWD ? wdr[top * L + em[j]] : wdl[l * L + ec[j]];
+                const int b = FWD ? wdl[top * L + ep[j]] : wdr[l * L + ec[j]];
+                in.wm[j] = okm[j] ? a : kInf;
+                in.wp[j] = okp[j] ? b : kInf;
             }
         }
     };
-    load(0);
-    for (int step = 0; step < NL; ++step) {
+    int prev[C];
+    bool changed = false;
+    auto process = [&](const LineIn<C> &in, int step, bool first) {
         const int l = FWD ? step : NL - 1 - step;
-        int cur[C], Pl[C], a[C];
-        int wc[C], wm[C], wp[C];
+        int a[C], t[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-            cur[j] = ncur[j]; Pl[j] = nP[j]; wc[j] = nwc[j]; wm[j] = nwm[j]; wp[j] = nwp[j];
-        }
-        if (step + 1 < NL) load(step + 1);
-
-        // Cross edges from the previous line (unused weights are kInf).
-#pragma unroll
-        for (int j = 0; j < C; ++j) a[j] = min(cur[j], prev[j] + wc[j]);
-        if (CONN == 8) {
+        for (int j = 0; j < C; ++j) a[j] = first ? in.cur[j] : min(in.cur[j], prev[j] + in.wc[j]);
+        if (CONN == 8 && !first) {
             int left_in = __shfl_up(prev[C - 1], 1);
             int right_in = __shfl_down(prev[0], 1);
-            if (lane == 0) left_in = kInf;
-            if (lane == 63) right_in = kInf;
+            left_in = lane == 0 ? kInf : left_in;
+            right_in = lane == 63 ? kInf : right_in;
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 const int pm = j > 0 ? prev[j - 1] : left_in;
                 const int pp = j < C - 1 ? prev[j + 1] : right_in;
-                a[j] = min(a[j], min(pm + wm[j], pp + wp[j]));
+                a[j] = min(a[j], min(pm + in.wm[j], pp + in.wp[j]));
             }
         }
-        // Along the line, increasing e.
-        int t[C];
-#pragma unroll
-        for (int j = 0; j < C; ++j) t[j] = a[j] - Pl[j];
-#pragma unroll
-        for (int j = 1; j < C; ++j) t[j] = min(t[j], t[j - 1]);
-        int ex = wave_excl_prefix_min(t[C - 1], row);
+        // Along the line: paths from e' <= e (prefix minimum of a - R) and
+        // from e' >= e (suffix minimum of a + R) are independent, so the two
+        // scans run interleaved.
+        int u[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            a[j] = min(t[j], ex) + Pl[j];
-            if (e0 + j >= L) a[j] = kInf;
+            t[j] = a[j] - in.P[j];
+            u[j] = a[j] + in.P[j];
         }
-        // Along the line, decreasing e.
 #pragma unroll
-        for (int j = 0; j < C; ++j) t[j] = a[j] + Pl[j];
-#pragma unroll
-        for (int j = C - 2; j >= 0; --j) t[j] = min(t[j], t[j + 1]);
-        ex = wave_excl_suffix_min(t[0], row);
-#pragma unroll
-        for (int j = 0; j < C; ++j) a[j] = min(t[j], ex) - Pl[j];
-        // Store improvements.
+        for (int j = 1; j < C; ++j) {
+            t[j] = min(t[j], t[j - 1]);
+            u[C - 1 - j] = min(u[C - 1 - j], u[C - j]);
+        }
+        const int2 ex = wave_excl_scans(t[C - 1], u[0], rm);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const int e = e0 + j;
-            if (e < L && a[j] < cur[j]) {
-                const int old = atomicMin(&d[l * ls + e * es], a[j]);
-                if (a[j] < old) changed = true;
-                a[j] = min(a[j], old);
+            a[j] = ok[j] ? min(min(t[j], ex.x) + in.P[j], min(u[j], ex.y) - in.P[j]) : kInf;
+            if (ok[j]) {
+                if (a[j] < in.cur[j]) changed = true;
+                atomicMin(&d[l * ls + ec[j] * es], a[j]);
             }
             prev[j] = a[j];
         }
+    };
+    // Ring of PF prefetched lines: slot (step % PF) holds line `step`.  Line
+    // indices past the end are clamped to the last line, so every load in the
+    // steady-state loop is unconditional and the wait counters stay exact.
+    LineIn<C> S[PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i) load(S[i], min(i, NL - 1));
+    process(S[0], 0, true);
+    load(S[0], min(PF, NL - 1));
+    int base = 1;
+    for (; base + PF <= NL; base += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int step = base + k;
+            process(S[(1 + k) % PF], step, false);
+            load(S[(1 + k) % PF], min(step + PF, NL - 1));
+        }
     }
+#pragma unroll
+    for (int k = 0; k < PF - 1; ++k)
+        if (base + k < NL) process(S[(1 + k) % PF], base + k, false);
     return changed;
 }
 
@@ -280,32 +314,71 @@ __device__ __forceinline__ bool code_used(int k) {
     return CONN == 8 || k == 1 || k == 3 || k == 4 || k == 6;
 }
 
-// True if some edge into (y, x) still relaxes its distance.
+// Path lengths into (y, x) through each neighbour k: d(q) + w(q, v), or kBig
+// where there is no such neighbour.  Loads use clamped in-image addresses and
+// are issued unconditionally; absent neighbours are masked afterwards.
 template <int CONN, bool G>
-__device__ bool pixel_violates(const GImg &g, const int *d, int Wp, int y, int x) {
-    const int dv = ldd<G>(&d[y * Wp + x]);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (!code_used<CONN>(k)) continue;
-        const int ny = y + code_dy(k), nx = x + code_dx(k);
-        if (ny < 0 || ny >= g.H || nx < 0 || nx >= g.W) continue;
-        if (ldd<G>(&d[ny * Wp + nx]) + nb_weight(g, y, x, k) < dv) return true;
+__device__ __forceinline__ void neighbour_paths(const GImg &g, const int *d, int Wp, int y, int x, int cand[8]) {
+    const int H = g.H, W = g.W;
+    const bool up = y > 0, dn = y + 1 < H, lf = x > 0, rt = x + 1 < W;
+    const int yu = up ? y - 1 : y, yd = dn ? y + 1 : y, xl = lf ? x - 1 : x, xr = rt ? x + 1 : x;
+    const int du = ldd<G>(&d[yu * Wp + x]), dl = ldd<G>(&d[y * Wp + xl]);
+    const int dr = ldd<G>(&d[y * Wp + xr]), dd = ldd<G>(&d[yd * Wp + x]);
+    const int wu = g.wd[yu * W + x], wl = g.wr[y * W + xl], wr = g.wr[y * W + x], wdn = g.wd[y * W + x];
+    cand[1] = up ? du + wu : kBig;
+    cand[3] = lf ? dl + wl : kBig;
+    cand[4] = rt ? dr + wr : kBig;
+    cand[6] = dn ? dd + wdn : kBig;
+    if (CONN == 8) {
+        const int dul = ldd<G>(&d[yu * Wp + xl]), dur = ldd<G>(&d[yu * Wp + xr]);
+        const int ddl = ldd<G>(&d[yd * Wp + xl]), ddr = ldd<G>(&d[yd * Wp + xr]);
+        const int wul = g.wdr[yu * W + xl], wur = g.wdl[yu * W + xr];
+        const int wdl_ = g.wdl[y * W + x], wdr_ = g.wdr[y * W + x];
+        cand[0] = (up && lf) ? dul + wul : kBig;
+        cand[2] = (up && rt) ? dur + wur : kBig;
+        cand[5] = (dn && lf) ? ddl + wdl_ : kBig;
+        cand[7] = (dn && rt) ? ddr + wdr_ : kBig;
+    } else {
+        cand[0] = cand[2] = cand[5] = cand[7] = kBig;
     }
-    return false;
+}
+
+// True if some edge into a pixel of the field still relaxes its distance.
+// Each thread takes U pixels at a time so that their loads overlap.
+template <int CONN, bool G>
+__device__ bool field_violates(const GImg &g, const int *d, int Wp) {
+    constexpr int U = 4;
+    bool bad = false;
+    const int N = g.N, W = g.W;
+    for (int base = threadIdx.x; base < N; base += blockDim.x * U) {
+        int m[U], dv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int v = min(base + k * (int)blockDim.x, N - 1);
+            const int y = v / W, x = v - y * W;
+            int cand[8];
+            neighbour_paths<CONN, G>(g, d, Wp, y, x, cand);
+            dv[k] = ldd<G>(&d[y * Wp + x]);
+            m[k] = cand[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) m[k] = min(m[k], cand[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) bad |= m[k] < dv[k];
+    }
+    return bad;
 }
 
 // Geodesic-tree parent of (y, x): the first neighbour, in ascending index
 // order, with d(q) + w(q, v) == d(v); kRootCode for a pixel at distance 0.
 template <int CONN>
 __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int x, int dv) {
+    int cand[8];
+    neighbour_paths<CONN, false>(g, d, Wp, y, x, cand);
+    uint32_t code = kRootCode;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (!code_used<CONN>(k)) continue;
-        const int ny = y + code_dy(k), nx = x + code_dx(k);
-        if (ny < 0 || ny >= g.H || nx < 0 || nx >= g.W) continue;
-        if (d[ny * Wp + nx] + nb_weight(g, y, x, k) == dv) return (uint32_t)k;
-    }
-    return kRootCode;
+    for (int k = 7; k >= 0; --k) code = cand[k] == dv ? (uint32_t)k : code;
+    return code;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -316,8 +389,11 @@ __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int 
 // a parallel check of every edge decides whether the fixed point is reached.
 // Returns the number of rounds, or -1 if max_rounds was hit.
 // ---------------------------------------------------------------------------------------------
-template <int CONN, int C, bool G = false>
-__device__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds) {
+// S is the size class of the image (its longer side is at most S); each
+// lane owns C = S / 64 elements of a line (at least one).
+template <int CONN, int S, bool G = false>
+__device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds) {
+    constexpr int C = S >= 64 ? S / 64 : 1;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     int rounds = 0;
@@ -334,12 +410,7 @@ __device__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds) {
         ++rounds;
         if (!__syncthreads_or(ch)) break;
         if (rounds >= max_rounds) return -1;
-        bool bad = false;
-        for (int v = tid; v < g.N && !bad; v += blockDim.x) {
-            const int y = v / g.W, x = v - y * g.W;
-            bad = pixel_violates<CONN, G>(g, d, Wp, y, x);
-        }
-        if (!__syncthreads_or(bad)) break;
+        if (!__syncthreads_or(field_violates<CONN, G>(g, d, Wp))) break;
     }
     return rounds;
 }
@@ -385,7 +456,7 @@ __device__ int64_t block_sum_i64(int64_t v, int64_t *red) {
 // With kGlobal the distance field lives in the output row itself (images too
 // large for LDS); otherwise in LDS, and the row is written once at the end.
 // ---------------------------------------------------------------------------------------------
-template <int CONN, int C, bool kGlobal>
+template <int CONN, int S, bool kGlobal>
 __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, const int32_t *src_list,
                                                               int src_base, int32_t *out, int max_rounds,
                                                               FrCtl *ctl) {
@@ -398,7 +469,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wd + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, C, kGlobal>(g, d, Wd, max_rounds);
+    const int r = relax_block<CONN, S, kGlobal>(g, d, Wd, max_rounds);
     if (threadIdx.x == 0) {
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
@@ -428,7 +499,7 @@ __global__ void k_fr_init(FrState fs) {
 // Geodesic centroid and the propagation from it (Section 3.3): propagate from
 // every border pixel, take the first pixel of maximal distance as the
 // centroid c, propagate from c into fs.dbuf.  One block.
-template <int CONN, int C>
+template <int CONN, int S>
 __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d, int max_rounds,
                                uint64_t *red) {
     const int H = g.H, W = g.W, N = g.N;
@@ -439,7 +510,7 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
         if (y == 0 || y == H - 1 || x == 0 || x == W - 1) d[y * Wp + x] = 0;
     }
     __syncthreads();
-    int r1 = relax_block<CONN, C>(g, d, Wp, max_rounds);
+    int r1 = relax_block<CONN, S>(g, d, Wp, max_rounds);
     // argmax with ties to the smallest index: minimise (INF - d, index)
     uint64_t best = ~0ull;
     for (int v = threadIdx.x; v < N; v += blockDim.x) {
@@ -453,7 +524,7 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
     __syncthreads();
     if (threadIdx.x == 0) d[(c / W) * Wp + c % W] = 0;
     __syncthreads();
-    int r2 = relax_block<CONN, C>(g, d, Wp, max_rounds);
+    int r2 = relax_block<CONN, S>(g, d, Wp, max_rounds);
     for (int v = threadIdx.x; v < N; v += blockDim.x) {
         const int y = v / W, x = v - y * W;
         fs.dbuf[v] = d[y * Wp + x];
@@ -465,11 +536,11 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
     }
 }
 
-template <int CONN, int C>
+template <int CONN, int S>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_setup(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
-    fr_setup_block<CONN, C>(g, Wp, fs, smem, max_rounds, red);
+    fr_setup_block<CONN, S>(g, Wp, fs, smem, max_rounds, red);
 }
 
 // rank[x] = position of x in the list sorted by decreasing d_c, ties by
@@ -496,10 +567,22 @@ __global__ void k_rank(const int32_t *dc, int N, int32_t *rank, int32_t *order) 
 // Least filled point (Section 3.4): argmin over x of (count[x], rank[x]).
 // Returns the pixel, or -1 when that point is filled (D is complete).
 __device__ int fr_select(const FrState &fs, uint64_t *red) {
+    constexpr int U = 8;  // independent loads in flight per thread
     uint64_t best = ~0ull;
-    for (int x = threadIdx.x; x < fs.N; x += blockDim.x) {
-        const uint64_t key = ((uint64_t)(uint32_t)fs.count[x] << 32) | (uint32_t)fs.rank[x];
-        best = key < best ? key : best;
+    const int step = blockDim.x * U;
+    for (int base = threadIdx.x; base < fs.N; base += step) {
+        int c[U], r[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int x = min(base + k * (int)blockDim.x, fs.N - 1);
+            c[k] = fs.count[x];
+            r[k] = fs.rank[x];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t key = ((uint64_t)(uint32_t)c[k] << 32) | (uint32_t)r[k];
+            best = key < best ? key : best;  // clamped duplicates change nothing
+        }
     }
     best = block_min_u64(best, red);
     if ((int)(best >> 32) >= fs.N) return -1;
@@ -508,7 +591,7 @@ __device__ int fr_select(const FrState &fs, uint64_t *red) {
 
 // One step of the filling-rate loop: select s, propagate from s, write the
 // tree as packed (d << 4 | parent code) words.  One block.
-template <int CONN, int C>
+template <int CONN, int S>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
@@ -530,11 +613,24 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wp + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, C>(g, d, Wp, max_rounds);
-    for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-        const int y = v / g.W, x = v - y * g.W;
-        const int dv = d[y * Wp + x];
-        fs.packed[v] = ((uint32_t)dv << 4) | parent_code<CONN>(g, d, Wp, y, x, dv);
+    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
+    {
+        // Tree words, U pixels per thread at a time: all loads first, then the stores.
+        constexpr int U = 4;
+        for (int base = threadIdx.x; base < g.N; base += blockDim.x * U) {
+            uint32_t w[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int v = min(base + k * (int)blockDim.x, g.N - 1);
+                const int y = v / g.W, x = v - y * g.W;
+                const int dv = d[y * Wp + x];
+                const uint32_t full = (v != s && fs.count[v] >= g.N) ? kFilledBit : 0u;
+                w[k] = tree_word(dv, parent_code<CONN>(g, d, Wp, y, x, dv)) | full;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (base + k * (int)blockDim.x < g.N) fs.packed[base + k * blockDim.x] = w[k];
+        }
     }
     if (threadIdx.x == 0) {
         if (r < 0) ctl->err = GAPD_ENOCONV;
@@ -542,64 +638,92 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
     }
 }
 
-// Redundancy fill for pixel v along its ancestors (Property 1).  pk holds the
-// packed tree with row stride pkW (W for global arrays, Wp for LDS).  Pairs
-// already marked are skipped, so every entry of D is written once.  Ancestors
-// are gathered KB at a time so their mask-word loads are in flight together.
-// Returns the number of new pairs.
-template <int KB>
-__device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, int v, int s) {
+// Block-wide copy of n words from global memory into LDS: 16-byte loads,
+// several in flight per thread before any is stored.
+__device__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
+    constexpr int U = 4;
+    const int n4 = n / 4;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    for (int base = threadIdx.x; base < n4; base += blockDim.x * U) {
+        uint4 t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) t[k] = s4[min(base + k * (int)blockDim.x, n4 - 1)];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (base + k * (int)blockDim.x < n4) d4[base + k * blockDim.x] = t[k];
+    }
+    for (int i = n4 * 4 + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Redundancy fill for pixel v along its ancestors (Property 1): every
+// ancestor u on the tree path from the source gives d(u,v) = d(s,v) - d(s,u).
+// pk holds the tree words with row stride pkW (W for global arrays, Wp for
+// LDS).  Pairs already marked are skipped, so every entry of D is written
+// once; an ancestor whose row was complete needs no look at the filled-pairs
+// matrix.  The walk moves one ancestor per iteration and keeps PF of them in
+// flight, so the loads of their filled-pairs words overlap.  Returns the
+// number of new pairs.
+template <int PF>
+__device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, int v, int s, int *cnt) {
     const int N = fs.N, MW = fs.MW;
-    const int vy = v / W, vx = v - vy * W;
-    int uy = vy, ux = vx;
-    const uint32_t pv = pk[vy * pkW + vx];
-    const int dv = (int)(pv >> 4);
-    uint32_t code = pv & 15u;
+    int uy = v / W, ux = v - uy * W;
+    const uint32_t wv = pk[uy * pkW + ux];
+    const int dv = tw_dist(wv);
+    uint32_t code = tw_code(wv);
     uint32_t *mrow = fs.mask + (size_t)v * MW;
     int32_t *Drow = fs.D + (size_t)v * N;
-    int nnew = 0;
-    bool end = (code == kRootCode);
-    while (!end) {
-        int ub[KB], du[KB];
-#pragma unroll
-        for (int i = 0; i < KB; ++i) {
-            ub[i] = -1;
-            du[i] = 0;
-            if (!end) {
-                const int k = (int)code;
-                uy += code_dy(k);
-                ux += code_dx(k);
-                const uint32_t pu = pk[uy * pkW + ux];
-                ub[i] = uy * W + ux;
-                du[i] = (int)(pu >> 4);
-                code = pu & 15u;
-                end = (code == kRootCode);
-            }
+    auto up = [&](int &u, int &du, uint32_t &bits) {
+        if (code == kRootCode) {
+            u = -1;
+            return;
         }
-        uint32_t wbits[KB];
+        uy += code_dy((int)code);
+        ux += code_dx((int)code);
+        const uint32_t pu = pk[uy * pkW + ux];
+        code = tw_code(pu);
+        u = uy * W + ux;
+        du = tw_dist(pu);
+        bits = 0xFFFFFFFFu;
+        if (!(pu & kFilledBit)) bits = mrow[u >> 5];
+    };
+    int ru[PF], rd[PF];
+    uint32_t rb[PF];
 #pragma unroll
-        for (int i = 0; i < KB; ++i) wbits[i] = ub[i] >= 0 ? mrow[ub[i] >> 5] : 0xFFFFFFFFu;
+    for (int k = 0; k < PF; ++k) up(ru[k], rd[k], rb[k]);
+    int nnew = 0;
+    bool alive = true;
+    while (alive) {
 #pragma unroll
-        for (int i = 0; i < KB; ++i) {
-            const int u = ub[i];
-            if (u < 0 || ((wbits[i] >> (u & 31)) & 1u)) continue;
-            const int val = dv - du[i];
-            Drow[u] = val;
-            fs.D[(size_t)u * N + v] = val;
-            atomicOr(&mrow[u >> 5], 1u << (u & 31));
-            if (u != s) {
-                atomicOr(&fs.mask[(size_t)u * MW + (v >> 5)], 1u << (v & 31));
-                atomicAdd(&fs.count[u], 1);
+        for (int k = 0; k < PF; ++k) {
+            const int u = ru[k];
+            alive = alive && u >= 0;
+            if (alive) {
+                if (!((rb[k] >> (u & 31)) & 1u)) {
+                    const int val = dv - rd[k];
+                    Drow[u] = val;
+                    fs.D[(size_t)u * N + v] = val;
+                    atomicOr(&mrow[u >> 5], 1u << (u & 31));
+                    if (u != s) {
+                        atomicOr(&fs.mask[(size_t)u * MW + (v >> 5)], 1u << (v & 31));
+                        atomicAdd(&cnt[u], 1);
+                    }
+                    ++nnew;
+                }
+                up(ru[k], rd[k], rb[k]);
             }
-            ++nnew;
         }
     }
     return nnew;
 }
 
-// Fill D along the current tree (many blocks).  The packed tree is staged in
-// LDS when it fits.  The source's own row becomes complete: block 0 marks it.
-template <bool kLds>
+// Fill D along the current tree (many blocks).  The tree words are staged in
+// LDS when they fit, and so are the count increments of the ancestors: the
+// few ancestors near the source collect thousands of increments per step,
+// which would serialise as same-address atomics in L2, so each block sums
+// them in LDS and adds its totals once.  The source's own row becomes
+// complete: block 0 marks it.
+template <bool kLds, bool kLdsCount>
 __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     extern __shared__ uint32_t spk[];
     __shared__ int64_t red[4];
@@ -607,17 +731,27 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     if (ctl->done) return;
     const int s = ctl->s, N = fs.N;
     const uint32_t *pk = fs.packed;
+    int *cnt = fs.count;
     if (kLds) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) spk[i] = fs.packed[i];
-        __syncthreads();
+        copy_to_lds(spk, fs.packed, N);
         pk = spk;
     }
+    if (kLdsCount) {
+        cnt = (int *)(spk + (kLds ? N : 0));
+        for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;
+    }
+    __syncthreads();
     int64_t mine = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
-        if (v == s || fs.count[v] >= N) continue;
-        const int n = fill_from<8>(fs, pk, W, W, v, s);
+        if (v == s || (pk[v] & kFilledBit)) continue;
+        const int n = fill_from<4>(fs, pk, W, W, v, s, cnt);
         if (n) atomicAdd(&fs.count[v], n);
         mine += n;
+    }
+    if (kLdsCount) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += blockDim.x)
+            if (cnt[i]) atomicAdd(&fs.count[i], cnt[i]);
     }
     const int64_t tot = block_sum_i64(mine, red);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&fs.ctl->filled, (unsigned long long)tot);
@@ -643,7 +777,7 @@ __device__ int find_image(const BImg *imgs, int B, int64_t item) {
     return lo;
 }
 
-template <int CONN, int C>
+template <int CONN, int S>
 __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg *imgs, int B, int32_t *out,
                                                                       int max_rounds, FrCtl *ctl) {
     extern __shared__ int smem[];
@@ -659,7 +793,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wp + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, C>(g, d, Wp, max_rounds);
+    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
     if (threadIdx.x == 0) {
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
@@ -674,7 +808,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
 // Batched filling rate: block b owns image b's whole loop (setup, then
 // select / propagate / tree / fill until D is complete).  The tree is packed
 // in LDS in place of the distances, so the fill walks ancestors in LDS.
-template <int CONN, int C>
+template <int CONN, int S>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
@@ -691,7 +825,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
         fs.count[i] = 1;
         fs.D[(size_t)i * N + i] = 0;
     }
-    fr_setup_block<CONN, C>(g, Wp, fs, d, max_rounds, red);
+    fr_setup_block<CONN, S>(g, Wp, fs, d, max_rounds, red);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -709,7 +843,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    int64_t nprop = 0, filled = 0, rounds = 0;
+    int64_t nprop = 0, nfilled = 0, rounds = 0;
     for (;;) {
         const int s = fr_select(fs, red);
         if (s < 0) break;
@@ -718,30 +852,34 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
         __syncthreads();
         if (threadIdx.x == 0) d[(s / W) * Wp + s % W] = 0;
         __syncthreads();
-        const int r = relax_block<CONN, C>(g, d, Wp, max_rounds);
+        const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
         rounds += r < 0 ? max_rounds : r;
         if (r < 0) {
             if (threadIdx.x == 0) fs.ctl->err = GAPD_ENOCONV;
             break;
         }
-        for (int v = threadIdx.x; v < N; v += blockDim.x) {
-            const int y = v / W, x = v - y * W;
-            codes[v] = (uint8_t)parent_code<CONN>(g, d, Wp, y, x, d[y * Wp + x]);
+        {
+            const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = __lane_id();
+            for (int y = wave; y < H; y += nw)
+                for (int x = lane; x < W; x += 64)
+                    codes[y * W + x] = (uint8_t)parent_code<CONN>(g, d, Wp, y, x, d[y * Wp + x]);
         }
         __syncthreads();
         for (int v = threadIdx.x; v < N; v += blockDim.x) {
             const int y = v / W, x = v - y * W;
-            d[y * Wp + x] = (int)(((uint32_t)d[y * Wp + x] << 4) | codes[v]);
+            const uint32_t full = (v != s && fs.count[v] >= N) ? kFilledBit : 0u;
+            d[y * Wp + x] = (int)(tree_word(d[y * Wp + x], codes[v]) | full);
         }
         __syncthreads();
         int64_t mine = 0;
         for (int v = threadIdx.x; v < N; v += blockDim.x) {
-            if (v == s || fs.count[v] >= N) continue;
-            const int n = fill_from<8>(fs, (const uint32_t *)d, Wp, W, v, s);
+            const int y = v / W, x = v - y * W;
+            if (v == s || ((uint32_t)d[y * Wp + x] & kFilledBit)) continue;
+            const int n = fill_from<4>(fs, (const uint32_t *)d, Wp, W, v, s, fs.count);
             if (n) atomicAdd(&fs.count[v], n);
             mine += n;
         }
-        filled += block_sum_i64(mine, red2);
+        nfilled += block_sum_i64(mine, red2);
         if (threadIdx.x == 0) fs.count[s] = N;
         uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
         for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
@@ -756,7 +894,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
     }
     if (threadIdx.x == 0) {
         fs.ctl->n_prop = nprop;
-        fs.ctl->filled = filled;
+        fs.ctl->filled = nfilled;
         fs.ctl->rounds += rounds;
         fs.ctl->done = 1;
     }
@@ -765,29 +903,36 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
 // ---------------------------------------------------------------------------------------------
 // Template dispatch on connectivity and elements per lane.
 // ---------------------------------------------------------------------------------------------
-inline int lane_chunk(int max_line) {
-    if (max_line <= 64) return 1;
-    if (max_line <= 128) return 2;
-    if (max_line <= 256) return 4;
-    return 8;
+// Size class: the smallest of 32, 64, 128, 192, 256, 512 that is >= the longer side.
+inline int size_class(int max_line) {
+    if (max_line <= 32) return 32;
+    if (max_line <= 64) return 64;
+    if (max_line <= 128) return 128;
+    if (max_line <= 192) return 192;
+    if (max_line <= 256) return 256;
+    return 512;
 }
 
 template <template <int, int> class F, typename... A>
 hipError_t dispatch(int conn, int max_line, A... args) {
-    const int c = lane_chunk(max_line);
+    const int c = size_class(max_line);
     if (conn == 4) {
         switch (c) {
-            case 1: return F<4, 1>::run(args...);
-            case 2: return F<4, 2>::run(args...);
-            case 4: return F<4, 4>::run(args...);
-            default: return F<4, 8>::run(args...);
+            case 32: return F<4, 32>::run(args...);
+            case 64: return F<4, 64>::run(args...);
+            case 128: return F<4, 128>::run(args...);
+            case 192: return F<4, 192>::run(args...);
+            case 256: return F<4, 256>::run(args...);
+            default: return F<4, 512>::run(args...);
         }
     }
     switch (c) {
-        case 1: return F<8, 1>::run(args...);
-        case 2: return F<8, 2>::run(args...);
-        case 4: return F<8, 4>::run(args...);
-        default: return F<8, 8>::run(args...);
+        case 32: return F<8, 32>::run(args...);
+        case 64: return F<8, 64>::run(args...);
+        case 128: return F<8, 128>::run(args...);
+        case 192: return F<8, 192>::run(args...);
+        case 256: return F<8, 256>::run(args...);
+        default: return F<8, 512>::run(args...);
     }
 }
 
@@ -797,32 +942,32 @@ hipError_t set_lds(K kernel, size_t bytes) {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int CONN, int C>
+template <int CONN, int S>
 struct RelaxRows {
     static hipError_t run(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
                           int max_rounds, FrCtl *ctl, hipStream_t st) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         if (lds <= kMaxLds) {
-            auto k = k_relax_rows<CONN, C, false>;
+            auto k = k_relax_rows<CONN, S, false>;
             hipError_t e = set_lds(k, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k, dim3(K), dim3(kRelaxThreads), lds, st, g, Wp, src_list, src_base, out,
                                max_rounds, ctl);
         } else {
-            hipLaunchKernelGGL((k_relax_rows<CONN, C, true>), dim3(K), dim3(kRelaxThreads), 0, st, g, g.W,
+            hipLaunchKernelGGL((k_relax_rows<CONN, S, true>), dim3(K), dim3(kRelaxThreads), 0, st, g, g.W,
                                src_list, src_base, out, max_rounds, ctl);
         }
         return hipGetLastError();
     }
 };
 
-template <int CONN, int C>
+template <int CONN, int S>
 struct FrSetup {
     static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        auto k1 = k_fr_setup<CONN, C>;
+        auto k1 = k_fr_setup<CONN, S>;
         hipError_t e = set_lds(k1, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
@@ -831,34 +976,43 @@ struct FrSetup {
     }
 };
 
-template <int CONN, int C>
+template <int CONN, int S>
 struct FrStep {
-    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
+    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        auto k1 = k_fr_step<CONN, C>;
+        auto k1 = k_fr_step<CONN, S>;
         hipError_t e = set_lds(k1, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        if (mid) {
+            e = hipEventRecord(mid, st);
+            if (e != hipSuccess) return e;
+        }
         const size_t pk = (size_t)g.N * sizeof(uint32_t);
         const int blocks = (g.N + 255) / 256;
-        if (pk <= kMaxLds) {
-            auto k2 = k_fr_fill<true>;
+        if (2 * pk <= kMaxLds) {
+            auto k2 = k_fr_fill<true, true>;
+            e = set_lds(k2, 2 * pk);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), 2 * pk, st, fs, g.W);
+        } else if (pk <= kMaxLds) {
+            auto k2 = k_fr_fill<true, false>;
             e = set_lds(k2, pk);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), pk, st, fs, g.W);
         } else {
-            hipLaunchKernelGGL(k_fr_fill<false>, dim3(blocks), dim3(256), 0, st, fs, g.W);
+            hipLaunchKernelGGL((k_fr_fill<false, false>), dim3(blocks), dim3(256), 0, st, fs, g.W);
         }
         return hipGetLastError();
     }
 };
 
-template <int CONN, int C>
+template <int CONN, int S>
 struct RelaxRowsBatched {
     static hipError_t run(const BImg *imgs, int B, int64_t n_items, size_t lds, int32_t *out, int max_rounds,
                           FrCtl *ctl, hipStream_t st) {
-        auto k = k_relax_rows_batched<CONN, C>;
+        auto k = k_relax_rows_batched<CONN, S>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         const int64_t gx = n_items < 65536 ? n_items : 65536;
@@ -869,10 +1023,10 @@ struct RelaxRowsBatched {
     }
 };
 
-template <int CONN, int C>
+template <int CONN, int S>
 struct FrBatched {
     static hipError_t run(const BImg *imgs, int B, size_t lds, int max_rounds, hipStream_t st) {
-        auto k = k_fr_batched<CONN, C>;
+        auto k = k_fr_batched<CONN, S>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(B), dim3(kRelaxThreads), lds, st, imgs, max_rounds);
@@ -952,8 +1106,8 @@ hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hip
     return dispatch<FrSetup>(g.conn, g.H > g.W ? g.H : g.W, g, fs, max_rounds, st);
 }
 
-hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
-    return dispatch<FrStep>(g.conn, g.H > g.W ? g.H : g.W, g, fs, max_rounds, st);
+hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
+    return dispatch<FrStep>(g.conn, g.H > g.W ? g.H : g.W, g, fs, max_rounds, st, mid);
 }
 
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line, size_t lds_bytes,

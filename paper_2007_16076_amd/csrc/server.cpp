@@ -166,7 +166,7 @@ int gapd_server::run_job(JobRec &j, hipStream_t st) {
 }
 
 void gapd_server::worker_loop() {
-    hipSetDevice(device);
+    (void)hipSetDevice(device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
     for (;;) {
@@ -201,8 +201,8 @@ void gapd_server::worker_loop() {
         cv_done.notify_all();
         cv_work.notify_all();
     }
-    hipStreamSynchronize(st);
-    hipStreamDestroy(st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
 }
 
 extern "C" {

@@ -40,7 +40,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_prop", ctypes.c_int64), ("n_prop_setup", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("centroid", ctypes.c_int32), ("_pad", ctypes.c_int32),
                 ("sources_out", ctypes.c_void_p), ("filled_out", ctypes.c_void_p),
-                ("ms_total", ctypes.c_float), ("ms_setup", ctypes.c_float)]
+                ("ms_total", ctypes.c_float), ("ms_setup", ctypes.c_float), ("ms_kernel", ctypes.c_float),
+                ("time_kernels", ctypes.c_int32), ("ms_step_kernels", ctypes.c_float),
+                ("ms_fill_kernels", ctypes.c_float), ("_pad2", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -133,6 +135,9 @@ class AllPairsStats:
     centroid: int
     ms_total: float
     ms_setup: float
+    ms_kernel: float
+    ms_step_kernels: float
+    ms_fill_kernels: float
 
 
 class Context:
@@ -189,7 +194,8 @@ class Context:
         _check(load_library().gapd_sssp(self._h, _dptr(src), K, _dptr(out)), self._h)
         return out
 
-    def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None):
+    def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None,
+                  time_kernels: bool = False):
         """The N x N distances array (device int32) and the call's statistics."""
         import torch
         if out is None:
@@ -198,8 +204,10 @@ class Context:
         st = Stats()
         st.sources_out = _dptr(sources_out) if sources_out is not None else None
         st.filled_out = _dptr(filled_out) if filled_out is not None else None
+        st.time_kernels = 1 if time_kernels else 0
         _check(load_library().gapd_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
-        return out, AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup)
+        return out, AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup,
+                                  st.ms_kernel, st.ms_step_kernels, st.ms_fill_kernels)
 
 
 def batched_workspace_size(shapes, C: int = 1, conn: int = CONN4, mode: int = MODE_NAIVE) -> int:
