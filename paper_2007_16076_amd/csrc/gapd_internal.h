@@ -73,6 +73,7 @@ struct FrState {
     int32_t *rank;             // N: position in the decreasing geodesic-extrema list
     int32_t *order;            // N: inverse of rank
     uint32_t *packed;          // N: tree words (distance, complete-row flag, parent direction)
+    uint32_t *full;            // ceil(N/32) words: bit i set once count[i] == N
     int32_t *dbuf;             // N: distances of the setup propagations
     int32_t *D;                // N * N output
     FrCtl *ctl;

@@ -116,6 +116,24 @@ __device__ __forceinline__ int ldd(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Block-wide copy of n words from global memory into LDS: 16-byte loads,
+// several in flight per thread before any is stored.
+__device__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
+    constexpr int U = 8;
+    const int n4 = n / 4;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    for (int base = threadIdx.x; base < n4; base += blockDim.x * U) {
+        uint4 t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) t[k] = s4[min(base + k * (int)blockDim.x, n4 - 1)];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (base + k * (int)blockDim.x < n4) d4[base + k * blockDim.x] = t[k];
+    }
+    for (int i = n4 * 4 + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_mov(int old, int v) {
     return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
@@ -314,17 +332,25 @@ __device__ __forceinline__ bool code_used(int k) {
     return CONN == 8 || k == 1 || k == 3 || k == 4 || k == 6;
 }
 
+// The four edge-weight arrays of the 4-/8-neighbourhood, from global memory
+// or from an LDS copy.
+struct NbW {
+    const uint16_t *wr, *wd, *wdr, *wdl;
+};
+__device__ inline NbW nbw_of(const GImg &g) { return NbW{g.wr, g.wd, g.wdr, g.wdl}; }
+
 // Path lengths into (y, x) through each neighbour k: d(q) + w(q, v), or kBig
 // where there is no such neighbour.  Loads use clamped in-image addresses and
 // are issued unconditionally; absent neighbours are masked afterwards.
 template <int CONN, bool G>
-__device__ __forceinline__ void neighbour_paths(const GImg &g, const int *d, int Wp, int y, int x, int cand[8]) {
+__device__ __forceinline__ void neighbour_paths(const GImg &g, const NbW &w, const int *d, int Wp, int y, int x,
+                                                int cand[8]) {
     const int H = g.H, W = g.W;
     const bool up = y > 0, dn = y + 1 < H, lf = x > 0, rt = x + 1 < W;
     const int yu = up ? y - 1 : y, yd = dn ? y + 1 : y, xl = lf ? x - 1 : x, xr = rt ? x + 1 : x;
     const int du = ldd<G>(&d[yu * Wp + x]), dl = ldd<G>(&d[y * Wp + xl]);
     const int dr = ldd<G>(&d[y * Wp + xr]), dd = ldd<G>(&d[yd * Wp + x]);
-    const int wu = g.wd[yu * W + x], wl = g.wr[y * W + xl], wr = g.wr[y * W + x], wdn = g.wd[y * W + x];
+    const int wu = w.wd[yu * W + x], wl = w.wr[y * W + xl], wr = w.wr[y * W + x], wdn = w.wd[y * W + x];
     cand[1] = up ? du + wu : kBig;
     cand[3] = lf ? dl + wl : kBig;
     cand[4] = rt ? dr + wr : kBig;
@@ -332,8 +358,8 @@ __device__ __forceinline__ void neighbour_paths(const GImg &g, const int *d, int
     if (CONN == 8) {
         const int dul = ldd<G>(&d[yu * Wp + xl]), dur = ldd<G>(&d[yu * Wp + xr]);
         const int ddl = ldd<G>(&d[yd * Wp + xl]), ddr = ldd<G>(&d[yd * Wp + xr]);
-        const int wul = g.wdr[yu * W + xl], wur = g.wdl[yu * W + xr];
-        const int wdl_ = g.wdl[y * W + x], wdr_ = g.wdr[y * W + x];
+        const int wul = w.wdr[yu * W + xl], wur = w.wdl[yu * W + xr];
+        const int wdl_ = w.wdl[y * W + x], wdr_ = w.wdr[y * W + x];
         cand[0] = (up && lf) ? dul + wul : kBig;
         cand[2] = (up && rt) ? dur + wur : kBig;
         cand[5] = (dn && lf) ? ddl + wdl_ : kBig;
@@ -343,38 +369,50 @@ __device__ __forceinline__ void neighbour_paths(const GImg &g, const int *d, int
     }
 }
 
-// True if some edge into a pixel of the field still relaxes its distance.
+// One pass over every pixel of the field: true if some edge still relaxes a
+// distance.  With TREE it also writes each pixel's tree word (its distance
+// and the code of its geodesic-tree parent: the first neighbour, in
+// ascending index order, with d(q) + w(q, v) == d(v); kRootCode at distance
+// 0) to tree[v]; once a pass finds no relaxable edge these words are final.
 // Each thread takes U pixels at a time so that their loads overlap.
-template <int CONN, bool G>
-__device__ bool field_violates(const GImg &g, const int *d, int Wp) {
-    constexpr int U = 4;
+template <int CONN, bool G, bool TREE>
+__device__ bool field_check(const GImg &g, const NbW &w, const int *d, int Wp, uint32_t *tree) {
+    constexpr int U = 8;
     bool bad = false;
     const int N = g.N, W = g.W;
     for (int base = threadIdx.x; base < N; base += blockDim.x * U) {
         int m[U], dv[U];
+        uint32_t code[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int v = min(base + k * (int)blockDim.x, N - 1);
             const int y = v / W, x = v - y * W;
             int cand[8];
-            neighbour_paths<CONN, G>(g, d, Wp, y, x, cand);
+            neighbour_paths<CONN, G>(g, w, d, Wp, y, x, cand);
             dv[k] = ldd<G>(&d[y * Wp + x]);
             m[k] = cand[0];
 #pragma unroll
             for (int j = 1; j < 8; ++j) m[k] = min(m[k], cand[j]);
+            if (TREE) {
+                code[k] = kRootCode;
+#pragma unroll
+                for (int j = 7; j >= 0; --j) code[k] = cand[j] == dv[k] ? (uint32_t)j : code[k];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) bad |= m[k] < dv[k];
+        for (int k = 0; k < U; ++k) {
+            bad |= m[k] < dv[k];
+            if (TREE && base + k * (int)blockDim.x < N) tree[base + k * blockDim.x] = tree_word(dv[k], code[k]);
+        }
     }
     return bad;
 }
 
-// Geodesic-tree parent of (y, x): the first neighbour, in ascending index
-// order, with d(q) + w(q, v) == d(v); kRootCode for a pixel at distance 0.
+// Geodesic-tree parent of (y, x) (see field_check).
 template <int CONN>
 __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int x, int dv) {
     int cand[8];
-    neighbour_paths<CONN, false>(g, d, Wp, y, x, cand);
+    neighbour_paths<CONN, false>(g, nbw_of(g), d, Wp, y, x, cand);
     uint32_t code = kRootCode;
 #pragma unroll
     for (int k = 7; k >= 0; --k) code = cand[k] == dv ? (uint32_t)k : code;
@@ -391,8 +429,12 @@ __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int 
 // ---------------------------------------------------------------------------------------------
 // S is the size class of the image (its longer side is at most S); each
 // lane owns C = S / 64 elements of a line (at least one).
-template <int CONN, int S, bool G = false>
-__device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds) {
+//
+// With TREE the edge checks also write the tree words to tree[]; *tree_done
+// tells whether the last check (the one that ended the loop) wrote them.
+template <int CONN, int S, bool G = false, bool TREE = false>
+__device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds, const NbW *nw = nullptr,
+                                          uint32_t *tree = nullptr, bool *tree_done = nullptr) {
     constexpr int C = S >= 64 ? S / 64 : 1;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -410,7 +452,11 @@ __device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int ma
         ++rounds;
         if (!__syncthreads_or(ch)) break;
         if (rounds >= max_rounds) return -1;
-        if (!__syncthreads_or(field_violates<CONN, G>(g, d, Wp))) break;
+        const NbW w = nw ? *nw : nbw_of(g);
+        if (!__syncthreads_or(field_check<CONN, G, TREE>(g, w, d, Wp, tree))) {
+            if (TREE) *tree_done = true;
+            break;
+        }
     }
     return rounds;
 }
@@ -493,7 +539,15 @@ __global__ void k_fr_init(FrState fs) {
         fs.mask[(size_t)i * fs.MW + (i >> 5)] = 1u << (i & 31);
         fs.count[i] = 1;
         fs.D[(size_t)i * fs.N + i] = 0;
+        if ((i & 31) == 0) fs.full[i >> 5] = fs.N == 1 ? 1u : 0u;
     }
+}
+
+// count[i] += inc, keeping the complete-row bitmap in step: the addition
+// that brings the count to N sets bit i.
+__device__ __forceinline__ void count_add(const FrState &fs, int i, int inc) {
+    const int old = atomicAdd(&fs.count[i], inc);
+    if (old < fs.N && old + inc >= fs.N) atomicOr(&fs.full[i >> 5], 1u << (i & 31));
 }
 
 // Geodesic centroid and the propagation from it (Section 3.3): propagate from
@@ -591,7 +645,7 @@ __device__ int fr_select(const FrState &fs, uint64_t *red) {
 
 // One step of the filling-rate loop: select s, propagate from s, write the
 // tree as packed (d << 4 | parent code) words.  One block.
-template <int CONN, int S>
+template <int CONN, int S, bool kStageW>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
@@ -609,51 +663,34 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
         ctl->n_prop += 1;
     }
     int *d = smem;
+    NbW w = nbw_of(g);
+    if (kStageW) {
+        // The edge checks and the tree pass read every weight of the
+        // neighbourhood: keep them in LDS next to the distance field.
+        const int half = (g.N + 1) / 2;  // u16 pairs per array
+        uint32_t *lw = (uint32_t *)(smem + g.H * Wp);
+        copy_to_lds(lw, (const uint32_t *)g.wr, half);
+        copy_to_lds(lw + half, (const uint32_t *)g.wd, half);
+        w.wr = (const uint16_t *)lw;
+        w.wd = (const uint16_t *)(lw + half);
+        if (CONN == 8) {
+            copy_to_lds(lw + 2 * half, (const uint32_t *)g.wdr, half);
+            copy_to_lds(lw + 3 * half, (const uint32_t *)g.wdl, half);
+            w.wdr = (const uint16_t *)(lw + 2 * half);
+            w.wdl = (const uint16_t *)(lw + 3 * half);
+        }
+    }
     fill_inf(d, g.H * Wp);
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wp + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
-    {
-        // Tree words, U pixels per thread at a time: all loads first, then the stores.
-        constexpr int U = 4;
-        for (int base = threadIdx.x; base < g.N; base += blockDim.x * U) {
-            uint32_t w[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int v = min(base + k * (int)blockDim.x, g.N - 1);
-                const int y = v / g.W, x = v - y * g.W;
-                const int dv = d[y * Wp + x];
-                const uint32_t full = (v != s && fs.count[v] >= g.N) ? kFilledBit : 0u;
-                w[k] = tree_word(dv, parent_code<CONN>(g, d, Wp, y, x, dv)) | full;
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k)
-                if (base + k * (int)blockDim.x < g.N) fs.packed[base + k * blockDim.x] = w[k];
-        }
-    }
+    bool tree_done = false;
+    const int r = relax_block<CONN, S, false, true>(g, d, Wp, max_rounds, &w, fs.packed, &tree_done);
+    if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, fs.packed);
     if (threadIdx.x == 0) {
         if (r < 0) ctl->err = GAPD_ENOCONV;
         ctl->rounds += r < 0 ? max_rounds : r;
     }
-}
-
-// Block-wide copy of n words from global memory into LDS: 16-byte loads,
-// several in flight per thread before any is stored.
-__device__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
-    constexpr int U = 4;
-    const int n4 = n / 4;
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-    for (int base = threadIdx.x; base < n4; base += blockDim.x * U) {
-        uint4 t[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) t[k] = s4[min(base + k * (int)blockDim.x, n4 - 1)];
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (base + k * (int)blockDim.x < n4) d4[base + k * blockDim.x] = t[k];
-    }
-    for (int i = n4 * 4 + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
 // Redundancy fill for pixel v along its ancestors (Property 1): every
@@ -664,7 +701,7 @@ __device__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
 // matrix.  The walk moves one ancestor per iteration and keeps PF of them in
 // flight, so the loads of their filled-pairs words overlap.  Returns the
 // number of new pairs.
-template <int PF>
+template <int PF, bool kCntLds>
 __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, int v, int s, int *cnt) {
     const int N = fs.N, MW = fs.MW;
     int uy = v / W, ux = v - uy * W;
@@ -706,7 +743,10 @@ __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, 
                     atomicOr(&mrow[u >> 5], 1u << (u & 31));
                     if (u != s) {
                         atomicOr(&fs.mask[(size_t)u * MW + (v >> 5)], 1u << (v & 31));
-                        atomicAdd(&cnt[u], 1);
+                        if (kCntLds)
+                            atomicAdd(&cnt[u], 1);
+                        else
+                            count_add(fs, u, 1);
                     }
                     ++nnew;
                 }
@@ -736,6 +776,19 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
         copy_to_lds(spk, fs.packed, N);
         pk = spk;
     }
+    __syncthreads();
+    // Flag the points whose rows were complete before this step (not the
+    // source, whose row this step completes), from the complete-row bitmap.
+    if (kLds) {
+        for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
+            uint32_t b = fs.full[w];
+            while (b) {
+                const int i = w * 32 + __ffs(b) - 1;
+                b &= b - 1;
+                if (i != s) spk[i] |= kFilledBit;
+            }
+        }
+    }
     if (kLdsCount) {
         cnt = (int *)(spk + (kLds ? N : 0));
         for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;
@@ -744,14 +797,14 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     int64_t mine = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
         if (v == s || (pk[v] & kFilledBit)) continue;
-        const int n = fill_from<4>(fs, pk, W, W, v, s, cnt);
-        if (n) atomicAdd(&fs.count[v], n);
+        const int n = fill_from<16, kLdsCount>(fs, pk, W, W, v, s, cnt);
+        if (n) count_add(fs, v, n);
         mine += n;
     }
     if (kLdsCount) {
         __syncthreads();
         for (int i = threadIdx.x; i < N; i += blockDim.x)
-            if (cnt[i]) atomicAdd(&fs.count[i], cnt[i]);
+            if (cnt[i]) count_add(fs, i, cnt[i]);
     }
     const int64_t tot = block_sum_i64(mine, red);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&fs.ctl->filled, (unsigned long long)tot);
@@ -761,7 +814,10 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
             const int lo = w * 32;
             mrow[w] = (N - lo >= 32) ? 0xFFFFFFFFu : ((1u << (N - lo)) - 1u);
         }
-        if (threadIdx.x == 0) fs.count[s] = N;
+        if (threadIdx.x == 0) {
+            fs.count[s] = N;
+            atomicOr(&fs.full[s >> 5], 1u << (s & 31));
+        }
     }
 }
 
@@ -875,12 +931,15 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, 
         for (int v = threadIdx.x; v < N; v += blockDim.x) {
             const int y = v / W, x = v - y * W;
             if (v == s || ((uint32_t)d[y * Wp + x] & kFilledBit)) continue;
-            const int n = fill_from<4>(fs, (const uint32_t *)d, Wp, W, v, s, fs.count);
-            if (n) atomicAdd(&fs.count[v], n);
+            const int n = fill_from<16, false>(fs, (const uint32_t *)d, Wp, W, v, s, fs.count);
+            if (n) count_add(fs, v, n);
             mine += n;
         }
         nfilled += block_sum_i64(mine, red2);
-        if (threadIdx.x == 0) fs.count[s] = N;
+        if (threadIdx.x == 0) {
+            fs.count[s] = N;
+            atomicOr(&fs.full[s >> 5], 1u << (s & 31));
+        }
         uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
         for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
             const int lo = w * 32;
@@ -981,10 +1040,19 @@ struct FrStep {
     static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        auto k1 = k_fr_step<CONN, S>;
-        hipError_t e = set_lds(k1, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
+        hipError_t e;
+        if (lds + wbytes <= kMaxLds) {
+            auto k1 = k_fr_step<CONN, S, true>;
+            e = set_lds(k1, lds + wbytes);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds + wbytes, st, g, Wp, fs, max_rounds);
+        } else {
+            auto k1 = k_fr_step<CONN, S, false>;
+            e = set_lds(k1, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        }
         if (mid) {
             e = hipEventRecord(mid, st);
             if (e != hipSuccess) return e;
@@ -1070,7 +1138,7 @@ FrState fr_workspace_layout(void *ws, int N) {
     f.order = (int32_t *)p; p += al256((size_t)N * 4);
     f.packed = (uint32_t *)p; p += al256((size_t)N * 4);
     f.dbuf = (int32_t *)p; p += al256((size_t)N * 4);
-    p += al256((size_t)N * 4);  // reserved
+    f.full = (uint32_t *)p; p += al256((size_t)N * 4);
     f.ctl = (FrCtl *)p;
     return f;
 }
