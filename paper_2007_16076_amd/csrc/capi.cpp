@@ -441,8 +441,8 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
     std::vector<BImg> bi(B);
     std::vector<int64_t> ioff(B);
     int64_t items = 0;
-    int max_line = 1;
-    size_t lds = 0;
+    int max_line = 1, maxN = 1;
+    size_t lds = 0, wbytes = 0;
     for (int i = 0; i < B; ++i) {
         const int b = order[i];
         const int N = H[b] * W[b];
@@ -456,14 +456,14 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
         x.item0 = items;
         items += N;
         max_line = std::max(max_line, std::max(H[b], W[b]));
-        size_t l = (size_t)H[b] * x.Wp * 4;
+        const size_t l = (size_t)H[b] * x.Wp * 4;
         if (mode == GAPD_MODE_TREE_FILL_FR) {
-            // distances (then tree words) and parent codes
-            l = l + (size_t)((N + 3) / 4) * 4;
             x.fr = fr_workspace_layout(frbase + p.fr_off[b], N);
             x.fr.D = out + out_offsets[b];
+            wbytes = std::max(wbytes, (size_t)(conn == 8 ? 4 : 2) * ((N + 1) / 2) * 4);
         }
         lds = std::max(lds, l);
+        maxN = std::max(maxN, N);
     }
     if (lds > kMaxLds) { g_create_error = "an image is too large for the batched kernels"; return GAPD_EINVAL; }
     const int max_rounds = max_rounds_for(1 << 30);
@@ -476,10 +476,29 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
     if (e == hipSuccess && mode == GAPD_MODE_TREE_FILL_FR) e = hipMemsetAsync(frbase, 0, p.fr_bytes, st);
     if (e == hipSuccess) e = launch_prep_batched(gw_dev, imgs_dev, ioff_dev, B, C, weight_mode, st);
     if (e == hipSuccess) {
-        if (mode == GAPD_MODE_NAIVE)
+        if (mode == GAPD_MODE_NAIVE) {
             e = launch_relax_rows_batched(bimg_dev, B, items, max_line, lds, conn, out, max_rounds, ctl_dev, st);
-        else
-            e = launch_fr_batched(bimg_dev, B, max_line, lds, conn, max_rounds, st);
+        } else {
+            // Images run their loops in lockstep; the host enqueues steps in
+            // chunks and reads how many images have finished between chunks.
+            e = launch_fr_batched_setup(bimg_dev, B, max_line, maxN, lds, conn, max_rounds, st);
+            const int chunk = std::max(1, env_int("GAPD_FR_CHUNK", 64));
+            int64_t enq = 0;
+            while (e == hipSuccess) {
+                for (int i = 0; i < chunk && e == hipSuccess; ++i)
+                    e = launch_fr_batched_step(bimg_dev, B, max_line, maxN, lds, wbytes, conn, max_rounds,
+                                               &ctl_dev->done, st);
+                enq += chunk;
+                FrCtl hc{};
+                if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl_dev, sizeof(FrCtl), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess || hc.done >= B) break;
+                if (enq > (int64_t)maxN + 2 * chunk) {
+                    g_create_error = "batched filling-rate loop did not terminate";
+                    return GAPD_EDEVICE;
+                }
+            }
+        }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { g_create_error = std::string("batched: ") + hipGetErrorString(e); return GAPD_EDEVICE; }

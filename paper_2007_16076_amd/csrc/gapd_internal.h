@@ -121,9 +121,15 @@ hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipS
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line,
                                      size_t lds_bytes, int conn, int32_t *out, int max_rounds, FrCtl *ctl,
                                      hipStream_t st);
-// Batched filling rate: one persistent workgroup per image.
-hipError_t launch_fr_batched(const BImg *imgs_dev, int B, int max_line, size_t lds_bytes, int conn,
-                             int max_rounds, hipStream_t st);
+// Batched filling rate, images in lockstep: the setup of every image, then
+// steps that each cover every image still running (one select+propagate
+// block per image, then the fills of all images in one launch).  lds is the
+// largest distance field (H * Wp * 4), wbytes the largest LDS weight copy;
+// batch_done counts the images whose loop has ended.
+hipError_t launch_fr_batched_setup(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, int conn,
+                                   int max_rounds, hipStream_t st);
+hipError_t launch_fr_batched_step(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, size_t wbytes,
+                                  int conn, int max_rounds, int *batch_done, hipStream_t st);
 
 // LDS row stride for an image of width W (odd, so column walks avoid bank conflicts).
 inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }

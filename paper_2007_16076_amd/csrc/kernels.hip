@@ -534,13 +534,19 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
 
 // D_mrk(i,i) = 1, count = 1, D(i,i) = 0 (Section 2; the filled-pairs matrix
 // must already be zero).
-__global__ void k_fr_init(FrState fs) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < fs.N; i += gridDim.x * blockDim.x) {
+__device__ void fr_init_range(const FrState &fs, int i0, int stride) {
+    for (int i = i0; i < fs.N; i += stride) {
         fs.mask[(size_t)i * fs.MW + (i >> 5)] = 1u << (i & 31);
         fs.count[i] = 1;
         fs.D[(size_t)i * fs.N + i] = 0;
         if ((i & 31) == 0) fs.full[i >> 5] = fs.N == 1 ? 1u : 0u;
     }
+}
+
+__global__ void k_fr_init(FrState fs) { fr_init_range(fs, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x); }
+
+__global__ void k_fr_init_b(const BImg *imgs) {
+    fr_init_range(imgs[blockIdx.y].fr, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // count[i] += inc, keeping the complete-row bitmap in step: the addition
@@ -597,11 +603,18 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_setup(GImg g, int Wp, FrSt
     fr_setup_block<CONN, S>(g, Wp, fs, smem, max_rounds, red);
 }
 
+template <int CONN, int S>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_setup_b(const BImg *imgs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    const BImg &bi = imgs[blockIdx.x];
+    fr_setup_block<CONN, S>(bi.g, bi.Wp, bi.fr, smem, max_rounds, red);
+}
+
 // rank[x] = position of x in the list sorted by decreasing d_c, ties by
 // increasing index (Section 3.3); order = inverse permutation.  Brute-force
 // counting over all pairs (N^2 comparisons, once per run).
-__global__ void k_rank(const int32_t *dc, int N, int32_t *rank, int32_t *order) {
-    __shared__ int32_t tile[256];
+__device__ void rank_block(const int32_t *dc, int N, int32_t *rank, int32_t *order, int32_t *tile) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int dx = x < N ? dc[x] : 0;
     int cnt = 0;
@@ -616,6 +629,18 @@ __global__ void k_rank(const int32_t *dc, int N, int32_t *rank, int32_t *order) 
         }
     }
     if (x < N) { rank[x] = cnt; order[cnt] = x; }
+}
+
+__global__ void k_rank(const int32_t *dc, int N, int32_t *rank, int32_t *order) {
+    __shared__ int32_t tile[256];
+    rank_block(dc, N, rank, order, tile);
+}
+
+__global__ void k_rank_b(const BImg *imgs) {
+    __shared__ int32_t tile[256];
+    const FrState &fs = imgs[blockIdx.y].fr;
+    if ((int)(blockIdx.x * blockDim.x) >= fs.N) return;
+    rank_block(fs.dbuf, fs.N, fs.rank, fs.order, tile);
 }
 
 // Least filled point (Section 3.4): argmin over x of (count[x], rank[x]).
@@ -645,16 +670,20 @@ __device__ int fr_select(const FrState &fs, uint64_t *red) {
 
 // One step of the filling-rate loop: select s, propagate from s, write the
 // tree as packed (d << 4 | parent code) words.  One block.
+// One step of the loop for one image, by one block.  batch_done (nullable)
+// counts the images of a batch whose loop has ended.
 template <int CONN, int S, bool kStageW>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
+__device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, uint64_t *red,
+                              int *batch_done) {
     FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     if (threadIdx.x == 0 && fs.filled_out && ctl->n_prop > 0) fs.filled_out[ctl->n_prop - 1] = ctl->filled;
     const int s = fr_select(fs, red);
     if (s < 0) {
-        if (threadIdx.x == 0) ctl->done = 1;
+        if (threadIdx.x == 0) {
+            ctl->done = 1;
+            if (batch_done) atomicAdd(batch_done, 1);
+        }
         return;
     }
     if (threadIdx.x == 0) {
@@ -691,6 +720,22 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
         if (r < 0) ctl->err = GAPD_ENOCONV;
         ctl->rounds += r < 0 ? max_rounds : r;
     }
+}
+
+template <int CONN, int S, bool kStageW>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    fr_step_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, red, nullptr);
+}
+
+// Every image of a batch takes its step at once: block b is image b.
+template <int CONN, int S, bool kStageW>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_step_b(const BImg *imgs, int max_rounds, int *batch_done) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    const BImg &bi = imgs[blockIdx.x];
+    fr_step_block<CONN, S, kStageW>(bi.g, bi.Wp, bi.fr, max_rounds, smem, red, batch_done);
 }
 
 // Redundancy fill for pixel v along its ancestors (Property 1): every
@@ -764,9 +809,7 @@ __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, 
 // them in LDS and adds its totals once.  The source's own row becomes
 // complete: block 0 marks it.
 template <bool kLds, bool kLdsCount>
-__global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
-    extern __shared__ uint32_t spk[];
-    __shared__ int64_t red[4];
+__device__ void fr_fill_block(const FrState &fs, int W, uint32_t *spk, int64_t *red, int chunk, int nchunks) {
     const FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     const int s = ctl->s, N = fs.N;
@@ -795,7 +838,7 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     }
     __syncthreads();
     int64_t mine = 0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
+    for (int v = chunk * blockDim.x + threadIdx.x; v < N; v += nchunks * blockDim.x) {
         if (v == s || (pk[v] & kFilledBit)) continue;
         const int n = fill_from<16, kLdsCount>(fs, pk, W, W, v, s, cnt);
         if (n) count_add(fs, v, n);
@@ -808,7 +851,7 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     }
     const int64_t tot = block_sum_i64(mine, red);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&fs.ctl->filled, (unsigned long long)tot);
-    if (blockIdx.x == 0) {
+    if (chunk == 0) {
         uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
         for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
             const int lo = w * 32;
@@ -819,6 +862,23 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
             atomicOr(&fs.full[s >> 5], 1u << (s & 31));
         }
     }
+}
+
+template <bool kLds, bool kLdsCount>
+__global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
+    extern __shared__ uint32_t spk[];
+    __shared__ int64_t red[4];
+    fr_fill_block<kLds, kLdsCount>(fs, W, spk, red, blockIdx.x, gridDim.x);
+}
+
+// Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
+template <bool kLds, bool kLdsCount>
+__global__ __launch_bounds__(256) void k_fr_fill_b(const BImg *imgs) {
+    extern __shared__ uint32_t spk[];
+    __shared__ int64_t red[4];
+    const BImg &bi = imgs[blockIdx.y];
+    if ((int)(blockIdx.x * blockDim.x) >= bi.fr.N) return;
+    fr_fill_block<kLds, kLdsCount>(bi.fr, bi.g.W, spk, red, blockIdx.x, (bi.fr.N + blockDim.x - 1) / blockDim.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -858,104 +918,6 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
     for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
         const int y = v / g.W, x = v - y * g.W;
         row[v] = d[y * Wp + x];
-    }
-}
-
-// Batched filling rate: block b owns image b's whole loop (setup, then
-// select / propagate / tree / fill until D is complete).  The tree is packed
-// in LDS in place of the distances, so the fill walks ancestors in LDS.
-template <int CONN, int S>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_batched(const BImg *imgs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    __shared__ int64_t red2[kRelaxThreads / 64];
-    const BImg &bi = imgs[blockIdx.x];
-    const GImg g = bi.g;
-    const FrState fs = bi.fr;
-    const int Wp = bi.Wp, H = g.H, W = g.W, N = g.N;
-    int *d = smem;
-    uint8_t *codes = (uint8_t *)(smem + H * Wp);
-    // D_mrk = I, count = 1, D(i,i) = 0
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        fs.mask[(size_t)i * fs.MW + (i >> 5)] = 1u << (i & 31);
-        fs.count[i] = 1;
-        fs.D[(size_t)i * N + i] = 0;
-    }
-    fr_setup_block<CONN, S>(g, Wp, fs, d, max_rounds, red);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // ranks by counting (fs.dbuf holds d_c)
-    for (int x = threadIdx.x; x < N; x += blockDim.x) {
-        const int dx = fs.dbuf[x];
-        int cnt = 0;
-        for (int y = 0; y < N; ++y) {
-            const int dy = fs.dbuf[y];
-            cnt += (dy > dx) || (dy == dx && y < x);
-        }
-        fs.rank[x] = cnt;
-        fs.order[cnt] = x;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    int64_t nprop = 0, nfilled = 0, rounds = 0;
-    for (;;) {
-        const int s = fr_select(fs, red);
-        if (s < 0) break;
-        ++nprop;
-        fill_inf(d, H * Wp);
-        __syncthreads();
-        if (threadIdx.x == 0) d[(s / W) * Wp + s % W] = 0;
-        __syncthreads();
-        const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
-        rounds += r < 0 ? max_rounds : r;
-        if (r < 0) {
-            if (threadIdx.x == 0) fs.ctl->err = GAPD_ENOCONV;
-            break;
-        }
-        {
-            const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = __lane_id();
-            for (int y = wave; y < H; y += nw)
-                for (int x = lane; x < W; x += 64)
-                    codes[y * W + x] = (uint8_t)parent_code<CONN>(g, d, Wp, y, x, d[y * Wp + x]);
-        }
-        __syncthreads();
-        for (int v = threadIdx.x; v < N; v += blockDim.x) {
-            const int y = v / W, x = v - y * W;
-            const uint32_t full = (v != s && fs.count[v] >= N) ? kFilledBit : 0u;
-            d[y * Wp + x] = (int)(tree_word(d[y * Wp + x], codes[v]) | full);
-        }
-        __syncthreads();
-        int64_t mine = 0;
-        for (int v = threadIdx.x; v < N; v += blockDim.x) {
-            const int y = v / W, x = v - y * W;
-            if (v == s || ((uint32_t)d[y * Wp + x] & kFilledBit)) continue;
-            const int n = fill_from<16, false>(fs, (const uint32_t *)d, Wp, W, v, s, fs.count);
-            if (n) count_add(fs, v, n);
-            mine += n;
-        }
-        nfilled += block_sum_i64(mine, red2);
-        if (threadIdx.x == 0) {
-            fs.count[s] = N;
-            atomicOr(&fs.full[s >> 5], 1u << (s & 31));
-        }
-        uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
-        for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
-            const int lo = w * 32;
-            mrow[w] = (N - lo >= 32) ? 0xFFFFFFFFu : ((1u << (N - lo)) - 1u);
-        }
-        // Counts and marks were updated by other waves through L2 atomics:
-        // release ours, wait for all, and drop stale L1 lines before the next select.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    if (threadIdx.x == 0) {
-        fs.ctl->n_prop = nprop;
-        fs.ctl->filled = nfilled;
-        fs.ctl->rounds += rounds;
-        fs.ctl->done = 1;
     }
 }
 
@@ -1092,12 +1054,49 @@ struct RelaxRowsBatched {
 };
 
 template <int CONN, int S>
-struct FrBatched {
-    static hipError_t run(const BImg *imgs, int B, size_t lds, int max_rounds, hipStream_t st) {
-        auto k = k_fr_batched<CONN, S>;
+struct FrBatchedSetup {
+    static hipError_t run(const BImg *imgs, int B, int maxN, size_t lds, int max_rounds, hipStream_t st) {
+        hipLaunchKernelGGL(k_fr_init_b, dim3((maxN + 255) / 256, B), dim3(256), 0, st, imgs);
+        auto k = k_fr_setup_b<CONN, S>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(B), dim3(kRelaxThreads), lds, st, imgs, max_rounds);
+        hipLaunchKernelGGL(k_rank_b, dim3((maxN + 255) / 256, B), dim3(256), 0, st, imgs);
+        return hipGetLastError();
+    }
+};
+
+template <int CONN, int S>
+struct FrBatchedStep {
+    static hipError_t run(const BImg *imgs, int B, int maxN, size_t lds, size_t wbytes, int max_rounds,
+                          int *batch_done, hipStream_t st) {
+        hipError_t e;
+        if (lds + wbytes <= kMaxLds) {
+            auto k1 = k_fr_step_b<CONN, S, true>;
+            e = set_lds(k1, lds + wbytes);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k1, dim3(B), dim3(kRelaxThreads), lds + wbytes, st, imgs, max_rounds, batch_done);
+        } else {
+            auto k1 = k_fr_step_b<CONN, S, false>;
+            e = set_lds(k1, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k1, dim3(B), dim3(kRelaxThreads), lds, st, imgs, max_rounds, batch_done);
+        }
+        const size_t pk = (size_t)maxN * sizeof(uint32_t);
+        const dim3 grid((maxN + 255) / 256, B);
+        if (2 * pk <= kMaxLds) {
+            auto k2 = k_fr_fill_b<true, true>;
+            e = set_lds(k2, 2 * pk);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k2, grid, dim3(256), 2 * pk, st, imgs);
+        } else if (pk <= kMaxLds) {
+            auto k2 = k_fr_fill_b<true, false>;
+            e = set_lds(k2, pk);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k2, grid, dim3(256), pk, st, imgs);
+        } else {
+            hipLaunchKernelGGL((k_fr_fill_b<false, false>), grid, dim3(256), 0, st, imgs);
+        }
         return hipGetLastError();
     }
 };
@@ -1184,10 +1183,16 @@ hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_item
     return dispatch<RelaxRowsBatched>(conn, max_line, imgs_dev, B, n_items, lds_bytes, out, max_rounds, ctl, st);
 }
 
-hipError_t launch_fr_batched(const BImg *imgs_dev, int B, int max_line, size_t lds_bytes, int conn, int max_rounds,
-                             hipStream_t st) {
+hipError_t launch_fr_batched_setup(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, int conn,
+                                   int max_rounds, hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    return dispatch<FrBatched>(conn, max_line, imgs_dev, B, lds_bytes, max_rounds, st);
+    return dispatch<FrBatchedSetup>(conn, max_line, imgs_dev, B, maxN, lds, max_rounds, st);
+}
+
+hipError_t launch_fr_batched_step(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, size_t wbytes,
+                                  int conn, int max_rounds, int *batch_done, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    return dispatch<FrBatchedStep>(conn, max_line, imgs_dev, B, maxN, lds, wbytes, max_rounds, batch_done, st);
 }
 
 }  // namespace gapd

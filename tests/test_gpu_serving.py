@@ -1,0 +1,114 @@
+"""GPU tests of the continuous-batching server.
+
+Each job's result must be identical (integers, tolerance 0) whether it runs
+alone or mixed with other jobs that overlap it on the device, and must equal
+the CPU oracle.  Admission is first come first served under the arena budget.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def G(torch_mod):
+    from paper_2007_16076_amd import gapd
+    gapd.load_library()
+    return gapd
+
+
+def make_jobs():
+    import synth
+    rng = np.random.default_rng(77)
+    big = synth.blob_image(rng, 64, 64)
+    # a long filling-rate job first: the later submissions arrive while it runs
+    jobs = [("fr", synth.blob_image(rng, 48, 48), None)]
+    for i in range(10):
+        kind = ["naive", "fr", "ms"][i % 3]
+        if kind == "ms":
+            src = np.sort(rng.choice(big.size, size=int(rng.integers(1, 40)), replace=False)).astype(np.int32)
+            jobs.append(("ms", big, src))
+        else:
+            side = int(rng.integers(12, 40))
+            jobs.append((kind, synth.blob_image(rng, side, side + int(rng.integers(0, 5))), None))
+    return jobs
+
+
+def submit(srv, G, job):
+    kind, img, src = job
+    if kind == "ms":
+        return srv.submit_multi_source(img, src)
+    return srv.submit_all_pairs(img, mode=G.MODE_TREE_FILL_FR if kind == "fr" else G.MODE_NAIVE)
+
+
+def test_mix_equals_alone_and_oracle(G, torch_mod, oracle_lib):
+    jobs = make_jobs()
+    # alone: one slot, one job at a time
+    alone = []
+    srv1 = G.Server(1 << 30, max_slots=1)
+    for job in jobs:
+        t = submit(srv1, G, job)
+        r = srv1.wait(t)
+        alone.append(srv1.result_tensor(r).cpu().numpy().copy())
+        srv1.release(t)
+    srv1.close()
+    # mixed: everything submitted at once to 4 slots
+    srv = G.Server(1 << 30, max_slots=4)
+    tickets = [submit(srv, G, job) for job in jobs]
+    spans = []
+    for job, t, ref in zip(jobs, tickets, alone):
+        r = srv.wait(t)
+        got = srv.result_tensor(r).cpu().numpy()
+        assert np.array_equal(got, ref)
+        spans.append((r.t_admit, r.t_done))
+        kind, img, src = job
+        if kind == "ms":
+            exp = oracle_lib.rows(img, src).reshape(-1)
+        else:
+            exp = oracle_lib.naive(img).reshape(-1)
+        assert np.array_equal(got, exp)
+        srv.release(t)
+    srv.close()
+    # at least two jobs were on the device at the same time
+    overlap = max(sum(1 for a, b in spans if a <= t0 < b) for t0, _ in spans)
+    assert overlap >= 2
+
+
+def test_admission_fifo_under_small_arena(G, torch_mod):
+    import synth
+    rng = np.random.default_rng(5)
+    imgs = [synth.blob_image(rng, 30, 30) for _ in range(6)]
+    # each naive job needs ~3.3 MB of output: the arena holds two at a time
+    srv = G.Server(8 << 20, max_slots=4)
+    tickets = [srv.submit_all_pairs(im) for im in imgs]
+    res = []
+    for t in tickets:
+        r = srv.wait(t)
+        res.append((r.t_submit, r.t_admit, r.t_done))
+        srv.release(t)   # frees room for the queued ones
+    srv.close()
+    admits = [a for _, a, _ in res]
+    assert admits == sorted(admits)               # first come, first served
+    assert all(s <= a <= d for s, a, d in res)
+
+
+def test_errors(G, torch_mod):
+    srv = G.Server(1 << 20, max_slots=2)
+    img = np.full((64, 64), 7, np.uint8)          # 64 MiB of output: never fits 1 MiB
+    with pytest.raises(G.GapdError) as e:
+        srv.submit_all_pairs(img)
+    assert e.value.status == G.ENOMEM
+    with pytest.raises(G.GapdError) as e:
+        srv.release(123456)
+    assert e.value.status == G.ENOTFOUND
+    with pytest.raises(G.GapdError) as e:
+        srv.submit_multi_source(np.ones((8, 8), np.uint8), np.array([64], np.int32))
+    assert e.value.status == G.EINVAL
+    srv.close()
