@@ -90,6 +90,10 @@ typedef struct {
     float    ms_step_kernels; /* sum of durations of the select+propagate launches        */
     float    ms_fill_kernels; /* sum of durations of the redundancy-fill launches         */
     int32_t  _pad2;
+    int64_t  n_prop_speculative; /* filling-rate mode: propagations computed ahead for
+                                    likely next sources (not counted in n_prop)          */
+    int64_t  n_cache_hits;  /* filling-rate steps whose propagation was such a tree, taken
+                               from the cache instead of being propagated again          */
 } gapd_stats;
 
 /* ---- single image ------------------------------------------------------------------------ */

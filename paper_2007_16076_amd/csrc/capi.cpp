@@ -179,7 +179,7 @@ int gapd_workspace_size(gapd_ctx *ctx, int mode, size_t *bytes) {
     if (!bytes) return fail(ctx, GAPD_EINVAL, "bytes is null");
     if (mode == GAPD_MODE_NAIVE) { *bytes = 0; return GAPD_OK; }
     if (mode != GAPD_MODE_TREE_FILL_FR) return fail(ctx, GAPD_EINVAL, "unknown mode");
-    *bytes = fr_workspace_bytes(ctx->N);
+    *bytes = fr_workspace_bytes(ctx->N, true);
     return GAPD_OK;
 }
 
@@ -214,7 +214,7 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
     gapd_stats local{};
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
-    s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0;
+    s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
     hipEvent_t e0, e1, e2;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
@@ -231,9 +231,9 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = ctx->N;
     } else {
-        const size_t need = fr_workspace_bytes(ctx->N);
+        const size_t need = fr_workspace_bytes(ctx->N, true);
         if (!ctx->ws || ctx->ws_bytes < need) return fail(ctx, GAPD_ENOMEM, "filling-rate workspace missing or too small");
-        FrState fs = fr_workspace_layout(ctx->ws, ctx->N);
+        FrState fs = fr_workspace_layout(ctx->ws, ctx->N, true);
         fs.D = out;
         fs.seq_out = s.sources_out;
         fs.filled_out = s.filled_out;
@@ -249,6 +249,8 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         s.n_prop_setup = 2;
         s.rounds = hc.rounds;
         s.centroid = hc.centroid;
+        s.n_prop_speculative = hc.spec_props;
+        s.n_cache_hits = hc.spec_hits;
         float ms = 0;
         if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s.ms_setup = ms;
     }

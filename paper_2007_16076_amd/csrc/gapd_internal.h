@@ -62,7 +62,11 @@ struct FrCtl {
     int64_t n_prop;     // propagations done by the main loop
     int64_t filled;     // a: filled unordered pairs
     int64_t rounds;     // sweep rounds summed over propagations
-    int64_t pad[3];
+    int32_t tree_slot;  // tree-cache slot holding the current source's tree, -1: the packed array
+    int32_t next_slot;  // round-robin cursor of the tree cache
+    int32_t spec_n;     // candidates listed for speculation this step
+    int32_t spec_hits;  // steps whose tree came from the cache
+    int64_t spec_props; // speculative propagations computed
 };
 
 // Device state of the filling-rate method for one image.
@@ -74,6 +78,13 @@ struct FrState {
     int32_t *order;            // N: inverse of rank
     uint32_t *packed;          // N: tree words (distance, complete-row flag, parent direction)
     uint32_t *full;            // ceil(N/32) words: bit i set once count[i] == N
+    // Tree cache for speculative propagations (null when not used): kSpecSlots
+    // trees of N words, the slot of each source (-1: none), the source of each
+    // slot (-1: empty) and the candidates listed by the current step.
+    uint32_t *cache;
+    int32_t *src_slot;
+    int32_t *slot_src;
+    int32_t *spec_list;
     int32_t *dbuf;             // N: distances of the setup propagations
     int32_t *D;                // N * N output
     FrCtl *ctl;
@@ -81,9 +92,16 @@ struct FrState {
     int64_t *filled_out;       // nullable, N
 };
 
-// Workspace layout of a single-image filling-rate run.
-size_t fr_workspace_bytes(int N);
-FrState fr_workspace_layout(void *ws, int N);
+// Speculation: each step lists the kSpecK least-filled points whose trees are
+// not cached; their propagations run beside the fill, into a cache of
+// kSpecSlots trees.  A tree depends on the image only, so a cached tree is
+// exactly the tree the step would compute.
+constexpr int kSpecK = 8;
+constexpr int kSpecSlots = 64;
+
+// Workspace layout of a single-image filling-rate run (spec: with the cache).
+size_t fr_workspace_bytes(int N, bool spec = false);
+FrState fr_workspace_layout(void *ws, int N, bool spec = false);
 
 // One image of a batch, as the batched kernels see it.
 struct BImg {

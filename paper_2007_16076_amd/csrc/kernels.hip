@@ -535,6 +535,11 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
 // D_mrk(i,i) = 1, count = 1, D(i,i) = 0 (Section 2; the filled-pairs matrix
 // must already be zero).
 __device__ void fr_init_range(const FrState &fs, int i0, int stride) {
+    if (fs.src_slot)
+        for (int i = i0; i < (fs.N > kSpecSlots ? fs.N : kSpecSlots); i += stride) {
+            if (i < fs.N) fs.src_slot[i] = -1;
+            if (i < kSpecSlots) fs.slot_src[i] = -1;
+        }
     for (int i = i0; i < fs.N; i += stride) {
         fs.mask[(size_t)i * fs.MW + (i >> 5)] = 1u << (i & 31);
         fs.count[i] = 1;
@@ -668,17 +673,81 @@ __device__ int fr_select(const FrState &fs, uint64_t *red) {
     return fs.order[(int)(best & 0xFFFFFFFFu)];
 }
 
+// Ascending bitonic sort of 2 * blockDim.x keys in LDS (blockDim.x a power of two).
+__device__ void block_bitonic_sort(uint64_t *k) {
+    const int n = 2 * blockDim.x, t = threadIdx.x;
+    for (int size = 2; size <= n; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            const int i = (t / stride) * 2 * stride + (t % stride), jj = i + stride;
+            const bool up = (i & size) == 0;
+            const uint64_t a = k[i], b = k[jj];
+            if ((a > b) == up) { k[i] = b; k[jj] = a; }
+        }
+    __syncthreads();
+}
+
+// fr_select, and from the same pass the candidates for speculation: up to
+// kSpecK points other than the selected one, with the smallest keys among
+// points whose rows are incomplete and whose trees are not cached.  Each
+// thread keeps its two best such keys; the block sorts the 2 * blockDim.x of
+// them.  The list goes to fs.spec_list, its length to *n_cand.
+__device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, int *n_cand) {
+    constexpr int U = 8;
+    constexpr uint64_t kNone = ~0ull;
+    uint64_t best = kNone, c1 = kNone, c2 = kNone;
+    const int step = blockDim.x * U;
+    for (int base = threadIdx.x; base < fs.N; base += step) {
+        int c[U], r[U], sl[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int x = min(base + k * (int)blockDim.x, fs.N - 1);
+            c[k] = fs.count[x];
+            r[k] = fs.rank[x];
+            sl[k] = fs.src_slot[x];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (base + k * (int)blockDim.x >= fs.N) continue;
+            const uint64_t key = ((uint64_t)(uint32_t)c[k] << 32) | (uint32_t)r[k];
+            best = key < best ? key : best;
+            if (sl[k] < 0 && c[k] < fs.N) {
+                if (key < c1) { c2 = c1; c1 = key; }
+                else if (key < c2) c2 = key;
+            }
+        }
+    }
+    best = block_min_u64(best, red);
+    if (c1 == best) { c1 = c2; c2 = kNone; }
+    else if (c2 == best) c2 = kNone;
+    keys[2 * threadIdx.x] = c1;
+    keys[2 * threadIdx.x + 1] = c2;
+    block_bitonic_sort(keys);
+    if (threadIdx.x < kSpecK) {
+        const uint64_t k = keys[threadIdx.x];
+        fs.spec_list[threadIdx.x] = k == kNone ? -1 : fs.order[(int)(k & 0xFFFFFFFFu)];
+    }
+    if (threadIdx.x == 0) {
+        int n = 0;
+        while (n < kSpecK && keys[n] != kNone) ++n;
+        *n_cand = n;
+    }
+    if ((int)(best >> 32) >= fs.N) return -1;
+    return fs.order[(int)(best & 0xFFFFFFFFu)];
+}
+
 // One step of the filling-rate loop: select s, propagate from s, write the
 // tree as packed (d << 4 | parent code) words.  One block.
 // One step of the loop for one image, by one block.  batch_done (nullable)
 // counts the images of a batch whose loop has ended.
-template <int CONN, int S, bool kStageW>
+template <int CONN, int S, bool kStageW, bool kSpec = false>
 __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, uint64_t *red,
-                              int *batch_done) {
+                              int *batch_done, uint64_t *keys = nullptr) {
     FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     if (threadIdx.x == 0 && fs.filled_out && ctl->n_prop > 0) fs.filled_out[ctl->n_prop - 1] = ctl->filled;
-    const int s = fr_select(fs, red);
+    __shared__ int n_cand;
+    const int s = kSpec ? fr_select_spec(fs, red, keys, &n_cand) : fr_select(fs, red);
     if (s < 0) {
         if (threadIdx.x == 0) {
             ctl->done = 1;
@@ -686,11 +755,18 @@ __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_
         }
         return;
     }
+    const int slot = kSpec ? fs.src_slot[s] : -1;
     if (threadIdx.x == 0) {
         if (fs.seq_out) fs.seq_out[ctl->n_prop] = s;
         ctl->s = s;
         ctl->n_prop += 1;
+        ctl->tree_slot = slot;
+        if (kSpec) {
+            ctl->spec_n = n_cand;
+            if (slot >= 0) ctl->spec_hits += 1;
+        }
     }
+    if (slot >= 0) return;  // the tree of s is already in the cache
     int *d = smem;
     NbW w = nbw_of(g);
     if (kStageW) {
@@ -727,6 +803,14 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
     fr_step_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, red, nullptr);
+}
+
+template <int CONN, int S, bool kStageW>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    __shared__ uint64_t keys[2 * kRelaxThreads];
+    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys);
 }
 
 // Every image of a batch takes its step at once: block b is image b.
@@ -809,14 +893,15 @@ __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, 
 // them in LDS and adds its totals once.  The source's own row becomes
 // complete: block 0 marks it.
 template <bool kLds, bool kLdsCount>
-__device__ void fr_fill_block(const FrState &fs, int W, uint32_t *spk, int64_t *red, int chunk, int nchunks) {
+__device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *spk, int64_t *red, int chunk,
+                              int nchunks) {
     const FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     const int s = ctl->s, N = fs.N;
-    const uint32_t *pk = fs.packed;
+    const uint32_t *pk = tree;
     int *cnt = fs.count;
     if (kLds) {
-        copy_to_lds(spk, fs.packed, N);
+        copy_to_lds(spk, tree, N);
         pk = spk;
     }
     __syncthreads();
@@ -868,7 +953,83 @@ template <bool kLds, bool kLdsCount>
 __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     extern __shared__ uint32_t spk[];
     __shared__ int64_t red[4];
-    fr_fill_block<kLds, kLdsCount>(fs, W, spk, red, blockIdx.x, gridDim.x);
+    fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
+}
+
+// Propagation of one speculative candidate into a free slot of the tree cache
+// (never the slot this step's fill reads).  One block.
+template <int CONN, int S, bool kStageW>
+__device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, int j) {
+    FrCtl *ctl = fs.ctl;
+    if (j >= ctl->spec_n) return;
+    const int c = fs.spec_list[j];
+    if (c < 0) return;
+    __shared__ int sh_slot;
+    if (threadIdx.x == 0) {
+        int sl;
+        do {
+            sl = atomicAdd(&ctl->next_slot, 1) % kSpecSlots;
+        } while (sl == ctl->tree_slot);
+        const int old = fs.slot_src[sl];
+        if (old >= 0) fs.src_slot[old] = -1;
+        fs.slot_src[sl] = -1;
+        sh_slot = sl;
+    }
+    __syncthreads();
+    const int sl = sh_slot;
+    uint32_t *tree = fs.cache + (size_t)sl * fs.N;
+    int *d = smem;
+    NbW w = nbw_of(g);
+    if (kStageW) {
+        const int half = (g.N + 1) / 2;
+        uint32_t *lw = (uint32_t *)(smem + g.H * Wp);
+        copy_to_lds(lw, (const uint32_t *)g.wr, half);
+        copy_to_lds(lw + half, (const uint32_t *)g.wd, half);
+        w.wr = (const uint16_t *)lw;
+        w.wd = (const uint16_t *)(lw + half);
+        if (CONN == 8) {
+            copy_to_lds(lw + 2 * half, (const uint32_t *)g.wdr, half);
+            copy_to_lds(lw + 3 * half, (const uint32_t *)g.wdl, half);
+            w.wdr = (const uint16_t *)(lw + 2 * half);
+            w.wdl = (const uint16_t *)(lw + 3 * half);
+        }
+    }
+    fill_inf(d, g.H * Wp);
+    __syncthreads();
+    if (threadIdx.x == 0) d[(c / g.W) * Wp + c % g.W] = 0;
+    __syncthreads();
+    bool tree_done = false;
+    const int r = relax_block<CONN, S, false, true>(g, d, Wp, max_rounds, &w, tree, &tree_done);
+    if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, tree);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // A candidate that does not converge stays uncached: if it is ever
+        // selected, its own step reports the error.
+        if (r < 0) return;
+        fs.slot_src[sl] = c;
+        fs.src_slot[c] = sl;
+        atomicAdd((unsigned long long *)&ctl->spec_props, 1ull);
+        atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)r);
+    }
+}
+
+// The fill of the current step (blocks kSpecK..) beside the speculative
+// propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
+// that the longer propagations start at once).
+template <int CONN, int S, bool kStageW, bool kLdsCount>
+__global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ int64_t red[4];
+    if (fs.ctl->done) return;
+    if ((int)blockIdx.x < kSpecK) {
+        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, blockIdx.x);
+        return;
+    }
+    const int slot = fs.ctl->tree_slot;
+    const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
+    fr_fill_block<true, kLdsCount>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
+                                   gridDim.x - kSpecK);
 }
 
 // Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
@@ -878,7 +1039,8 @@ __global__ __launch_bounds__(256) void k_fr_fill_b(const BImg *imgs) {
     __shared__ int64_t red[4];
     const BImg &bi = imgs[blockIdx.y];
     if ((int)(blockIdx.x * blockDim.x) >= bi.fr.N) return;
-    fr_fill_block<kLds, kLdsCount>(bi.fr, bi.g.W, spk, red, blockIdx.x, (bi.fr.N + blockDim.x - 1) / blockDim.x);
+    fr_fill_block<kLds, kLdsCount>(bi.fr, bi.fr.packed, bi.g.W, spk, red, blockIdx.x,
+                                   (bi.fr.N + blockDim.x - 1) / blockDim.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -999,29 +1161,56 @@ struct FrSetup {
 
 template <int CONN, int S>
 struct FrStep {
+    template <bool kStageW, bool kLdsCount>
+    static hipError_t launch_fill_spec(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
+                                       size_t lds, int blocks) {
+        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(kSpecK + blocks), dim3(256), lds, st, g, Wp, fs, max_rounds);
+        return hipGetLastError();
+    }
+
+    template <bool kStageW>
+    static hipError_t launch_step(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
+                                  size_t lds) {
+        const bool spec = fs.cache && (size_t)g.N * sizeof(uint32_t) <= kMaxLds;
+        auto k1 = spec ? k_fr_step_spec<CONN, S, kStageW> : k_fr_step<CONN, S, kStageW>;
+        hipError_t e = set_lds(k1, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        return hipGetLastError();
+    }
+
     static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
-        hipError_t e;
-        if (lds + wbytes <= kMaxLds) {
-            auto k1 = k_fr_step<CONN, S, true>;
-            e = set_lds(k1, lds + wbytes);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds + wbytes, st, g, Wp, fs, max_rounds);
-        } else {
-            auto k1 = k_fr_step<CONN, S, false>;
-            e = set_lds(k1, lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
-        }
+        hipError_t e = lds + wbytes <= kMaxLds ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes)
+                                               : launch_step<false>(g, Wp, fs, max_rounds, st, lds);
+        if (e != hipSuccess) return e;
         if (mid) {
             e = hipEventRecord(mid, st);
             if (e != hipSuccess) return e;
         }
         const size_t pk = (size_t)g.N * sizeof(uint32_t);
         const int blocks = (g.N + 255) / 256;
-        if (2 * pk <= kMaxLds) {
+        if (fs.cache && pk <= kMaxLds) {
+            // the fill beside the speculative propagations
+            const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
+            if (2 * pk <= kMaxLds) {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
+                else
+                    e = launch_fill_spec<false, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
+            } else {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
+                else
+                    e = launch_fill_spec<false, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
+            }
+            if (e != hipSuccess) return e;
+        } else if (2 * pk <= kMaxLds) {
             auto k2 = k_fr_fill<true, true>;
             e = set_lds(k2, 2 * pk);
             if (e != hipSuccess) return e;
@@ -1121,12 +1310,15 @@ GImgW weight_block_layout(void *dev, int H, int W, int conn) {
     return w;
 }
 
-size_t fr_workspace_bytes(int N) {
+size_t fr_workspace_bytes(int N, bool spec) {
     const size_t MW = ((size_t)N + 31) / 32;
-    return al256((size_t)N * MW * 4) + 6 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
+    size_t b = al256((size_t)N * MW * 4) + 6 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
+    if (spec)
+        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + al256(kSpecSlots * 4) + al256(kSpecK * 4);
+    return b;
 }
 
-FrState fr_workspace_layout(void *ws, int N) {
+FrState fr_workspace_layout(void *ws, int N, bool spec) {
     char *p = (char *)ws;
     FrState f{};
     f.N = N;
@@ -1138,7 +1330,13 @@ FrState fr_workspace_layout(void *ws, int N) {
     f.packed = (uint32_t *)p; p += al256((size_t)N * 4);
     f.dbuf = (int32_t *)p; p += al256((size_t)N * 4);
     f.full = (uint32_t *)p; p += al256((size_t)N * 4);
-    f.ctl = (FrCtl *)p;
+    f.ctl = (FrCtl *)p; p += al256(sizeof(FrCtl));
+    if (spec) {
+        f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * N * 4);
+        f.src_slot = (int32_t *)p; p += al256((size_t)N * 4);
+        f.slot_src = (int32_t *)p; p += al256(kSpecSlots * 4);
+        f.spec_list = (int32_t *)p;
+    }
     return f;
 }
 

@@ -90,7 +90,7 @@ size_t job_bytes(const gapd_job &j, size_t *elems) {
     const size_t N = (size_t)j.H * j.W;
     size_t b = al256(N * j.C) + weight_block_bytes(j.H, j.W) + al256(sizeof(FrCtl));
     if (j.kind == GAPD_JOB_ALL_PAIRS) {
-        if (j.mode == GAPD_MODE_TREE_FILL_FR) b += fr_workspace_bytes((int)N);
+        if (j.mode == GAPD_MODE_TREE_FILL_FR) b += fr_workspace_bytes((int)N, true);
         *elems = N * N;
     } else {
         b += al256(sizeof(int32_t) * (size_t)j.K);
@@ -143,8 +143,8 @@ int gapd_server::run_job(JobRec &j, hipStream_t st) {
     const int max_rounds = max_rounds_for(N);
     if (s.kind == GAPD_JOB_ALL_PAIRS) {
         if (s.mode == GAPD_MODE_TREE_FILL_FR) {
-            FrState fs = fr_workspace_layout(p, N);
-            p += fr_workspace_bytes(N);
+            FrState fs = fr_workspace_layout(p, N, true);
+            p += fr_workspace_bytes(N, true);
             fs.D = (int32_t *)p;
             j.dev_out = fs.D;
             FrCtl hc{};
