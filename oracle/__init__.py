@@ -4,7 +4,9 @@ This package wraps ``gapd_oracle.c``, a plain C implementation of what the
 GPU library computes, written from the paper (Noyel, Angulo, Jeulin, "Fast
 computation of all pairs of geodesic distances"): Dijkstra propagations,
 Floyd-Warshall for tiny images, the naive method, the geodesic centroid and
-extrema list, and the filling-rate method with its redundancy fill.
+extrema list, the filling-rate method with its redundancy fill, and with the
+same fill the geodesic extrema method and the spiral methods (with their
+random draws passed in).
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import it.  It shares no code with the GPU library and never imports it;
@@ -60,6 +62,9 @@ def _load():
             "gapd_oracle_parents": [P, i32, i32, i32, i32, i32, P, P],
             "gapd_oracle_extrema": [P, i32, i32, i32, i32, i32, P, P, P, P],
             "gapd_oracle_filling_rate": [P, i32, i32, i32, i32, i32, P, P, P, P, P, P, i64],
+            "gapd_oracle_extrema_method": [P, i32, i32, i32, i32, i32, P, P, P, P, P, i64],
+            "gapd_oracle_spiral": [P, i32, i32, i32, i32, i32, i32, P, i64, P, P, P, P, i64],
+            "gapd_oracle_spiral_turn": [i32, i32, i32, P, P],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -195,3 +200,55 @@ def filling_rate(image, conn=4, wmode=None, max_steps: int = -1) -> FillingRate:
                                                  _ptr(n), _ptr(c), _ptr(rk), int(max_steps)), "filling_rate")
     k = int(n[0])
     return FillingRate(D, seq[:k].copy(), a[:k].copy(), k, int(c[0]), rk, st == TRUNCATED)
+
+
+@dataclass
+class TreeMethod:
+    D: np.ndarray            # N x N int32 (partly written if truncated)
+    sequence: np.ndarray     # sources, one per propagation
+    filled: np.ndarray       # a(t): filled pairs after each propagation
+    n_prop: int              # propagations in the loop (setup not included)
+    centroid: int            # -1 for the spiral methods
+    truncated: bool
+
+
+def extrema_method(image, conn=4, wmode=None, max_steps: int = -1) -> TreeMethod:
+    """The geodesic extrema method (two setup propagations, then the farthest
+    unfilled point from the centroid, least filled among ties)."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    N = H * W
+    D = np.full((N, N), -1, dtype=np.int32)
+    seq = np.full(N, -1, dtype=np.int32)
+    a = np.zeros(N, dtype=np.int64)
+    n = np.zeros(1, dtype=np.int64)
+    c = np.zeros(1, dtype=np.int32)
+    st = _check(_load().gapd_oracle_extrema_method(_ptr(image), H, W, C, conn, wmode, _ptr(D), _ptr(seq), _ptr(a),
+                                                   _ptr(n), _ptr(c), int(max_steps)), "extrema_method")
+    k = int(n[0])
+    return TreeMethod(D, seq[:k].copy(), a[:k].copy(), k, int(c[0]), st == TRUNCATED)
+
+
+def spiral(image, rnd, h: int = 0, conn=4, wmode=None, max_steps: int = -1) -> TreeMethod:
+    """The spiral method (h <= 1) or the spiral method with repulsion h (the
+    paper's is 3); ``rnd`` holds the uniform uint32 draws, one per propagation."""
+    image, H, W, C = _img(image)
+    wmode = default_wmode(image) if wmode is None else wmode
+    N = H * W
+    rnd = np.ascontiguousarray(rnd, dtype=np.uint32)
+    D = np.full((N, N), -1, dtype=np.int32)
+    seq = np.full(N, -1, dtype=np.int32)
+    a = np.zeros(N, dtype=np.int64)
+    n = np.zeros(1, dtype=np.int64)
+    st = _check(_load().gapd_oracle_spiral(_ptr(image), H, W, C, conn, wmode, int(h), _ptr(rnd), rnd.size,
+                                           _ptr(D), _ptr(seq), _ptr(a), _ptr(n), int(max_steps)), "spiral")
+    k = int(n[0])
+    return TreeMethod(D, seq[:k].copy(), a[:k].copy(), k, -1, st == TRUNCATED)
+
+
+def spiral_turn(H: int, W: int, k: int):
+    """Pixels of spiral turn k in turn order, and whether the turn is a closed frame."""
+    out = np.empty(2 * (H + W) + 4, dtype=np.int32)
+    cyc = np.zeros(1, dtype=np.int32)
+    n = _load().gapd_oracle_spiral_turn(H, W, k, _ptr(out), _ptr(cyc))
+    return out[:n].copy(), bool(cyc[0])

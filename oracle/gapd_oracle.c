@@ -20,7 +20,10 @@
  *   - the filling-rate method (Section 3.4, algorithm "filling"), with the
  *     geodesic centroid and the decreasing list of geodesic extrema
  *     (Section 3.3), and the redundancy fill along geodesic trees
- *     (Section 2, Property 1).
+ *     (Section 2, Property 1);
+ *   - with the same fill, the geodesic extrema method (Section 3.3,
+ *     algorithm "extrema") and the spiral methods without and with repulsion
+ *     (Sections 3.1 and 3.2), whose random draws are inputs.
  *
  * Readings of the paper taken here (where it is silent or ambiguous):
  *   - pixel index i = y*W + x; no wrap-around at the image border;
@@ -35,7 +38,14 @@
  *   - the extrema list orders pixels by decreasing distance from the
  *     centroid, ties by increasing index; "Ext[x]" is x's position (rank);
  *   - the filling rate of a point is carried as the integer count of filled
- *     entries of its row (diagonal included), which has the same argmin.
+ *     entries of its row (diagonal included), which has the same argmin;
+ *   - extrema method: among the unfilled points at the greatest distance
+ *     from the centroid, the least filled, then the smallest index;
+ *   - spiral turns are listed clockwise from their top-left corner; a random
+ *     draw r (uniform 32 bits) picks member floor(r |S| / 2^32) of S in that
+ *     order; repulsion h removes from S the turn pixels 1 .. h-1 positions
+ *     away from s on either side (cyclically on a closed frame); a point is
+ *     "filled" when its row of D is complete.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -321,37 +331,87 @@ int gapd_oracle_extrema(const uint8_t *img, int H, int W, int C, int conn, int w
     return st;
 }
 
-/* The filling-rate method (Section 3.4, algorithm "filling").
- *   D          N*N int32 output (every entry written exactly once)
- *   seq_out    N int32, the source of each propagation (nullable)
- *   a_out      N int64, filled pairs a after each propagation (nullable;
- *              Section 2, eq. _a)
- *   n_prop     number of propagations in the loop (the two setup propagations
- *              of the centroid and extrema are not included)
- *   max_steps  stop after this many propagations (<0: no limit); the call then
- *              returns OR_TRUNCATED and D is only partly written
- * The filled-pairs matrix D_mrk (Section 2) is kept as one byte per entry and
- * the per-point filling rate tau(x) (eq. filling_rate_pt) as the integer
- * numerator count[x] = sum_k D_mrk(k, x).  */
-int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, int wmode,
-                             int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
-                             int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
+/* ---- spiral turns (Section 3.1) ------------------------------------------------------- */
+
+/* Spiral turn k of an H x W image: the one-pixel-wide frame of the pixels
+ * whose distance to the image border, min(y, x, H-1-y, W-1-x), is k (k = 0 is
+ * the outermost).  Listed clockwise from its top-left corner (k,k): the top
+ * row left to right, the right column downwards, the bottom row right to
+ * left, the left column upwards.  A turn of one row or one column is listed
+ * left to right or top to bottom.  Returns the length, 0 if the turn does not
+ * exist.  *cyclic is set when the list closes on itself (a proper frame). */
+int gapd_oracle_spiral_turn(int H, int W, int k, int32_t *out, int *cyclic) {
+    const int top = k, left = k, bottom = H - 1 - k, right = W - 1 - k;
+    int n = 0;
+    if (cyclic) *cyclic = 0;
+    if (k < 0 || top > bottom || left > right) return 0;
+    if (top == bottom) {
+        for (int x = left; x <= right; ++x) out[n++] = top * W + x;
+        return n;
+    }
+    if (left == right) {
+        for (int y = top; y <= bottom; ++y) out[n++] = y * W + left;
+        return n;
+    }
+    if (cyclic) *cyclic = 1;
+    for (int x = left; x <= right; ++x) out[n++] = top * W + x;
+    for (int y = top + 1; y <= bottom; ++y) out[n++] = y * W + right;
+    for (int x = right - 1; x >= left; --x) out[n++] = bottom * W + x;
+    if (ORACLE_MUTANT == 10) return n;  /* mutant: the left column is dropped */
+    for (int y = bottom - 1; y > top; --y) out[n++] = y * W + left;
+    return n;
+}
+
+/* ---- the tree-based methods: one loop, three selection rules --------------------------- */
+
+#define OR_RULE_FILLING 0  /* Section 3.4, algorithm "filling"                          */
+#define OR_RULE_EXTREMA 1  /* Section 3.3, algorithm "extrema"                          */
+#define OR_RULE_SPIRAL  2  /* Section 3.1 "spiral" and 3.2 "spiral with repulsion"        */
+
+/* State of the spiral selection: the current turn and the list S of its
+ * pixels that are still candidates (in_s, by position along the turn). */
+typedef struct {
+    int turn;        /* -1: no turn selected yet */
+    int len, cyclic;
+    int32_t *pix;    /* pixels of the turn, in turn order */
+    uint8_t *in_s;   /* membership in S, by position */
+} or_spiral;
+
+/* Every method below has the same body (Section 2): compute the geodesic
+ * tree from the selected source s, fill D along it by Property 1, then update
+ * the filled-pairs matrix D_mrk and the per-point counts.  Only the choice of
+ * s differs.
+ *   rule       OR_RULE_*
+ *   h          spiral only: repulsion distance; after s is drawn, the turn
+ *              pixels at 1 .. h-1 positions on either side of s leave S
+ *              (h <= 1: plain spiral method)
+ *   rnd        spiral only: one uniform 32-bit draw per selection; draw r
+ *              picks the floor(r * |S| / 2^32)-th member of S in turn order
+ *   n_rnd      length of rnd; the call fails with OR_EINVAL if it runs out
+ * Returns OR_TRUNCATED when max_steps (>= 0) stops the loop early. */
+static int or_tree_methods(const uint8_t *img, int H, int W, int C, int conn, int wmode, int rule, int h,
+                           const uint32_t *rnd, int64_t n_rnd, int32_t *D, int32_t *seq_out, int64_t *a_out,
+                           int64_t *n_prop, int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
     or_graph g;
     int st = or_graph_init(&g, img, H, W, C, conn, wmode);
     if (st) return st;
     if (!D || !n_prop) return OR_EINVAL;
+    if (rule == OR_RULE_SPIRAL && !rnd && n_rnd > 0) return OR_EINVAL;
     const int64_t N = g.N;
     uint8_t *mrk = (uint8_t *)calloc((size_t)(N * N), 1);
     int64_t *count = (int64_t *)malloc((size_t)N * sizeof(int64_t));
     int32_t *rank = (int32_t *)malloc((size_t)N * sizeof(int32_t));
     int32_t *parent = (int32_t *)malloc((size_t)N * sizeof(int32_t));
     int64_t *da = (int64_t *)malloc((size_t)N * sizeof(int64_t));
-    int64_t *db = (int64_t *)malloc((size_t)N * sizeof(int64_t));
-    if (!mrk || !count || !rank || !parent || !da || !db) { st = OR_ENOMEM; goto done; }
+    int64_t *dc = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    or_spiral sp = {-1, 0, 0, (int32_t *)malloc((size_t)(2 * (H + W) + 4) * sizeof(int32_t)),
+                    (uint8_t *)calloc((size_t)(2 * (H + W) + 4), 1)};
+    if (!mrk || !count || !rank || !parent || !da || !dc || !sp.pix || !sp.in_s) { st = OR_ENOMEM; goto done; }
 
-    /* Compute the decreasing list of geodesic extrema (Section 3.3). */
+    /* The geodesic centroid and the decreasing list of geodesic extrema
+     * (Section 3.3); dc keeps the distances from the centroid. */
     int32_t c;
-    st = gapd_oracle_extrema(img, H, W, C, conn, wmode, &c, da, db, rank);
+    st = gapd_oracle_extrema(img, H, W, C, conn, wmode, &c, da, dc, rank);
     if (st) goto done;
     if (centroid_out) *centroid_out = c;
     if (rank_out) memcpy(rank_out, rank, (size_t)N * sizeof(int32_t));
@@ -361,11 +421,65 @@ int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, 
     int64_t filled = 0, t = 0;
     *n_prop = 0;
     for (;;) {
-        /* B = argmin tau; among several, the greatest extremum (smallest rank). */
-        int64_t s = 0;
-        for (int64_t x = 1; x < N; ++x)
-            if (count[x] < count[s] || (count[x] == count[s] && ORACLE_MUTANT != 5 && rank[x] < rank[s])) s = x;
-        if (count[s] == N) break; /* the least filled point is filled: D is filled */
+        int64_t s = -1;
+        if (rule == OR_RULE_FILLING) {
+            /* B = argmin tau; among several, the greatest extremum (smallest rank). */
+            s = 0;
+            for (int64_t x = 1; x < N; ++x)
+                if (count[x] < count[s] || (count[x] == count[s] && ORACLE_MUTANT != 5 && rank[x] < rank[s])) s = x;
+            if (count[s] == N) break; /* the least filled point is filled: D is filled */
+        } else if (rule == OR_RULE_EXTREMA) {
+            /* Ext without its filled points; B = its points at the greatest
+             * distance from the centroid; s = the least filled of B (then the
+             * smallest index). */
+            for (int64_t x = 0; x < N; ++x) {
+                if (count[x] == N) continue;
+                if (s < 0 || dc[x] > dc[s]) { s = x; continue; }
+                if (dc[x] == dc[s] && (ORACLE_MUTANT == 9 ? count[x] > count[s] : count[x] < count[s])) s = x;
+            }
+            if (s < 0) break; /* every point is filled */
+        } else {
+            /* Remove the points of S which are filled. */
+            int64_t ns = 0;
+            for (int p = 0; p < sp.len; ++p) {
+                if (sp.in_s[p] && count[sp.pix[p]] == N) sp.in_s[p] = 0;
+                ns += sp.in_s[p];
+            }
+            if (ns == 0) {
+                /* S is empty: the most exterior turn that is not yet filled,
+                 * and S = its pixels that are not yet filled. */
+                int k = -1;
+                for (int64_t x = 0; x < N; ++x) {
+                    if (count[x] == N) continue;
+                    const int y = (int)(x / W), xx = (int)(x % W);
+                    int b = y < xx ? y : xx;
+                    if (H - 1 - y < b) b = H - 1 - y;
+                    if (W - 1 - xx < b) b = W - 1 - xx;
+                    if (k < 0 || b < k) k = b;
+                }
+                if (k < 0) break; /* D is filled */
+                sp.turn = k;
+                sp.len = gapd_oracle_spiral_turn(H, W, k, sp.pix, &sp.cyclic);
+                for (int p = 0; p < sp.len; ++p) {
+                    sp.in_s[p] = count[sp.pix[p]] < N;
+                    ns += sp.in_s[p];
+                }
+            }
+            /* Select a source point s randomly in S. */
+            if (t >= n_rnd) { st = OR_EINVAL; goto done; }
+            int64_t j = (int64_t)(((uint64_t)rnd[t] * (uint64_t)ns) >> 32), pos = -1;
+            for (int p = 0; p < sp.len; ++p)
+                if (sp.in_s[p] && j-- == 0) { pos = p; break; }
+            s = sp.pix[pos];
+            /* Repulsion: the h-1 turn pixels on either side of s leave S. */
+            for (int dd = 1; dd < h; ++dd)
+                for (int side = -1; side <= 1; side += 2) {
+                    int64_t p = pos + side * dd;
+                    if (sp.cyclic) p = ((p % sp.len) + sp.len) % sp.len;
+                    else if (p < 0 || p >= sp.len) continue;
+                    if (ORACLE_MUTANT != 11 || side > 0) sp.in_s[p] = 0;
+                }
+        }
         if (max_steps >= 0 && t >= max_steps) { st = OR_TRUNCATED; break; }
 
         /* Compute the geodesic tree from s. */
@@ -395,6 +509,46 @@ int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, 
         *n_prop = t;
     }
 done:
-    free(mrk); free(count); free(rank); free(parent); free(da); free(db);
+    free(mrk); free(count); free(rank); free(parent); free(da); free(dc); free(sp.pix); free(sp.in_s);
     return st;
+}
+
+/* The filling-rate method (Section 3.4, algorithm "filling").
+ *   D          N*N int32 output (every entry written exactly once)
+ *   seq_out    N int32, the source of each propagation (nullable)
+ *   a_out      N int64, filled pairs a after each propagation (nullable;
+ *              Section 2, eq. _a)
+ *   n_prop     number of propagations in the loop (the two setup propagations
+ *              of the centroid and extrema are not included)
+ *   max_steps  stop after this many propagations (<0: no limit); the call then
+ *              returns OR_TRUNCATED and D is only partly written
+ * The filled-pairs matrix D_mrk (Section 2) is kept as one byte per entry and
+ * the per-point filling rate tau(x) (eq. filling_rate_pt) as the integer
+ * numerator count[x] = sum_k D_mrk(k, x).  */
+int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                             int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
+                             int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
+    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_FILLING, 0, NULL, 0, D, seq_out, a_out, n_prop,
+                           centroid_out, rank_out, max_steps);
+}
+
+/* The geodesic extrema method (Section 3.3, algorithm "extrema"): the source
+ * is the unfilled point farthest from the geodesic centroid, the least filled
+ * among equally far ones.  Arguments as for gapd_oracle_filling_rate. */
+int gapd_oracle_extrema_method(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                               int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
+                               int32_t *centroid_out, int64_t max_steps) {
+    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_EXTREMA, 0, NULL, 0, D, seq_out, a_out, n_prop,
+                           centroid_out, NULL, max_steps);
+}
+
+/* The spiral method (Section 3.1, algorithm "spiral"; h <= 1) and the spiral
+ * method with repulsion (Section 3.2; the paper's h is 3): sources drawn at
+ * random in the most exterior spiral turn not yet filled.  rnd holds n_rnd
+ * uniform 32-bit draws, one per propagation (N always suffice). */
+int gapd_oracle_spiral(const uint8_t *img, int H, int W, int C, int conn, int wmode, int h,
+                       const uint32_t *rnd, int64_t n_rnd, int32_t *D, int32_t *seq_out, int64_t *a_out,
+                       int64_t *n_prop, int64_t max_steps) {
+    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_SPIRAL, h, rnd, n_rnd, D, seq_out, a_out, n_prop,
+                           NULL, NULL, max_steps);
 }

@@ -2,7 +2,8 @@
 
 Each mutant is the oracle built with one deliberate error planted at compile
 time (a dropped term, a reversed tie rule, a one-sided fill, ...).  The pins of
-``test_oracle.py`` are run against it in a subprocess and must fail.
+``test_oracle.py`` and ``test_oracle_methods.py`` are run against it in a
+subprocess and must fail.
 """
 import os
 import subprocess
@@ -21,6 +22,9 @@ MUTANTS = {
     6: "centroid ties go to the largest index",
     7: "border propagation omits the bottom row",
     8: "multiband weight drops the constant 1",
+    9: "extrema method takes the most filled of the farthest points",
+    10: "spiral turns drop their left column",
+    11: "spiral repulsion removes the pixels on one side of s only",
 }
 
 
@@ -31,6 +35,7 @@ def test_pins_reject_mutant(tmp_path, k):
     lib = oracle.build(out=str(tmp_path / f"libmutant{k}.so"), mutant=k)
     env = dict(os.environ, GAPD_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                        os.path.join(ROOT, "tests", "test_oracle.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_methods.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {k} ({MUTANTS[k]}) passed every pin"
