@@ -190,26 +190,37 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
     n_prop = s0.n_prop
     step_ms = float(np.mean([s.ms_step_kernels for s in fst])) / max(n_prop, 1)
     fill_ms = float(np.mean([s.ms_fill_kernels for s in fst])) / max(n_prop, 1)
-    rounds = s0.rounds / max(n_prop + 2, 1)
+    hits, n_spec = int(s0.n_cache_hits), int(s0.n_prop_speculative)
+    spec = hits > 0 or n_spec > 0
+    # rounds per propagation, over every propagation computed (setup, main
+    # loop misses, speculative)
+    rounds = s0.rounds / max(n_prop - hits + n_spec + 2, 1)
     # Per-launch algorithmic work (units stated in the design doc):
     #   fill: the D entries and mask bits the whole run writes once, averaged per launch;
     #   step: |E_dir| x rounds relaxations (add + min) of one propagation.
     fill_bytes = (4.0 * N * N + N * N / 8.0) / max(n_prop, 1)
     roof_fill = roofline_hbm(fill_bytes, fill_ms)
-    roof_fill.update(kernel="k_fr_fill (redundancy fill along the geodesic tree)",
+    fill_name = "k_fr_fill_spec" if spec else "k_fr_fill"
+    roof_fill.update(kernel=fill_name + " (redundancy fill along the geodesic tree"
+                     + (", beside the speculative propagations)" if spec else ")"),
                      algorithmic_bytes_per_launch=round(fill_bytes), avg_launch_ms=round(fill_ms, 5),
-                     traffic=measured_traffic(workload, "k_fr_fill<"))
-    step_ops = 2.0 * E_dir * rounds
+                     traffic=measured_traffic(workload, fill_name + "<"))
+    # a step launch propagates only when its source's tree was not cached
+    step_ops = 2.0 * E_dir * rounds * (n_prop - hits) / max(n_prop, 1)
     ach = step_ops / (step_ms * 1e-3) / 1e12
     roof_step = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
-                 "frac": round(ach / VALU_PEAK_TOPS, 6), "traffic": measured_traffic(workload, "k_fr_step<"),
-                 "kernel": "k_fr_step (least-filled select + one propagation + tree, one workgroup)",
+                 "frac": round(ach / VALU_PEAK_TOPS, 6),
+                 "traffic": measured_traffic(workload, "k_fr_step_spec<" if spec else "k_fr_step<"),
+                 "kernel": ("k_fr_step_spec" if spec else "k_fr_step")
+                 + " (least-filled select + one propagation + tree unless cached, one workgroup)",
                  "algorithmic_ops_per_launch": round(step_ops), "avg_launch_ms": round(step_ms, 5)}
     dominant, other = (roof_step, roof_fill) if step_ms >= fill_ms else (roof_fill, roof_step)
     value = N * N / (np.mean(fr_ms) * 1e-3)
     line.update(value=value, unit="distance entries/s", ms_per_step=round(float(np.mean(fr_ms)), 3),
                 p50_ms=round(pct(fr_ms, 50), 3), p99_ms=round(pct(fr_ms, 99), 3),
                 n_prop=int(n_prop), n_prop_setup=int(s0.n_prop_setup),
+                n_prop_speculative=n_spec, n_cache_hits=hits,
+                cache_hit_rate=round(hits / max(n_prop - 1, 1), 4),
                 propagation_saving_vs_naive=round(1.0 - (n_prop + s0.n_prop_setup) / N, 4),
                 fr_setup_ms=round(float(np.mean([s.ms_setup for s in fst])), 3),
                 fr_loop_kernel_ms={"select_propagate": round(step_ms * n_prop, 3),

@@ -64,6 +64,12 @@ extern "C" {
 #define GAPD_W_1PL1 1
 #define GAPD_MODE_NAIVE        0   /* N propagations, one row of D each (Section 1)          */
 #define GAPD_MODE_TREE_FILL_FR 1   /* filling-rate method (Section 3.4, algorithm filling)  */
+#define GAPD_MODE_TREE_FILL_EXTREMA 2 /* geodesic extrema method (Section 3.3, algorithm
+                                         extrema): the unfilled point farthest from the
+                                         geodesic centroid, the least filled (then the
+                                         smallest index) among equally far ones         */
+#define GAPD_MODE_TREE_FILL_SPIRAL 3 /* spiral methods (Sections 3.1, 3.2): only through
+                                        gapd_all_pairs_spiral, which takes the draws  */
 
 typedef struct gapd_ctx gapd_ctx;
 typedef struct gapd_server gapd_server;
@@ -109,9 +115,11 @@ int gapd_create(const uint8_t *image, int H, int W, int C, int conn, int weight_
 /* Use this HIP stream (a hipStream_t passed as void*) for later calls. */
 int gapd_set_stream(gapd_ctx *ctx, void *hip_stream);
 
-/* Bytes of caller-provided device workspace that gapd_all_pairs(mode) needs
- * (0 for the naive mode).  The filling-rate workspace holds the filled-pairs
- * bit matrix D_mrk (Section 2), N*ceil(N/32)*4 bytes, plus O(N) arrays. */
+/* Bytes of caller-provided device workspace that gapd_all_pairs(mode) or
+ * gapd_all_pairs_spiral needs (0 for the naive mode; the same for the three
+ * tree modes).  It holds the filled-pairs bit matrix D_mrk (Section 2),
+ * N*ceil(N/32)*4 bytes, a cache of 128 geodesic trees (4N bytes each) and
+ * O(N) arrays. */
 int gapd_workspace_size(gapd_ctx *ctx, int mode, size_t *bytes);
 
 /* Hand the context a DEVICE workspace of at least gapd_workspace_size bytes,
@@ -128,10 +136,30 @@ int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out);
 
 /* Every entry of the N x N distances array D.  out: DEVICE pointer to N*N
  * int32.  mode GAPD_MODE_NAIVE runs N propagations; GAPD_MODE_TREE_FILL_FR
- * runs the filling-rate method and needs the workspace.  Both give the same,
- * unique D.  st: nullable host struct.  Returns when the result is complete
- * on the stream (the call synchronises the stream). */
+ * runs the filling-rate method, GAPD_MODE_TREE_FILL_EXTREMA the geodesic
+ * extrema method; both need the workspace.  All give the same, unique D
+ * (Section 2, Property 1).  GAPD_MODE_TREE_FILL_SPIRAL is refused here
+ * (GAPD_EINVAL): it needs draws.  st: nullable host struct.  Returns when the
+ * result is complete on the stream (the call synchronises the stream). */
 int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
+
+/* The spiral method (Section 3.1, algorithm spiral) for h <= 1, and the
+ * spiral method with repulsion (Section 3.2; the paper uses h = 3) for h >= 2.
+ * Turn k is the frame of the pixels at distance k from the image border,
+ * listed clockwise from its top-left corner (one row or column: left to
+ * right, top to bottom).  Each step removes the filled points from S; when S
+ * is empty it takes the outermost turn with an unfilled point and sets S to
+ * its unfilled points; draw t (the t-th propagation) picks member
+ * floor(draws[t] * |S| / 2^32) of S in turn order; with repulsion the turn
+ * pixels 1 .. h-1 positions away from the source on either side (cyclically
+ * on a closed frame) leave S.
+ *   h      0 <= h <= 65536
+ *   draws  DEVICE pointer to N uniform uint32 draws, caller-owned, read only
+ *          (N always suffice: every propagation completes its source's row)
+ *   out    DEVICE pointer to N*N int32
+ * Needs the workspace of gapd_workspace_size(GAPD_MODE_TREE_FILL_SPIRAL).
+ * No setup propagations (st->n_prop_setup = 0, st->centroid = -1). */
+int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *out, gapd_stats *st);
 
 /* Release the context and its device memory (not the caller's buffers). */
 void gapd_destroy(gapd_ctx *ctx);
@@ -148,9 +176,11 @@ int gapd_batched_workspace_size(const int32_t *H, const int32_t *W, int B, int C
                                 size_t *bytes);
 
 /* All-pairs distances of B images in one pass: naive mode runs every
- * (image, source) propagation of the batch in one kernel launch; the
- * filling-rate mode runs one persistent workgroup per image, each owning its
- * image's sequential loop.
+ * (image, source) propagation of the batch in one kernel launch; the tree
+ * modes (GAPD_MODE_TREE_FILL_FR, GAPD_MODE_TREE_FILL_EXTREMA) run the images'
+ * sequential loops in lockstep, each step one launch with a workgroup per
+ * unfinished image (select and propagate) and one fill launch over all
+ * images.  Other modes give GAPD_EINVAL.
  *   images_packed: HOST, the B images back to back (H[b]*W[b]*C bytes each);
  *   H, W:          HOST, B sizes each;
  *   out:           DEVICE int32; image b's N_b x N_b array starts at
@@ -172,7 +202,8 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
 typedef struct {
     int            kind;        /* GAPD_JOB_ALL_PAIRS or GAPD_JOB_MULTI_SOURCE              */
     int            H, W, C, conn, weight_mode;
-    int            mode;        /* all-pairs jobs: GAPD_MODE_*                              */
+    int            mode;        /* all-pairs jobs: GAPD_MODE_NAIVE, _TREE_FILL_FR or
+                                   _TREE_FILL_EXTREMA (others: GAPD_EINVAL)                 */
     const uint8_t *image;       /* HOST, H*W*C bytes; copied at submit                      */
     const int32_t *sources;     /* HOST, K ids (multi-source jobs); copied at submit        */
     int            K;
@@ -181,7 +212,7 @@ typedef struct {
 typedef struct {
     int32_t *dev_out;           /* DEVICE result inside the arena: N*N or K*N int32          */
     size_t   elems;
-    int64_t  n_prop;            /* all-pairs filling-rate jobs: loop propagations           */
+    int64_t  n_prop;            /* all-pairs jobs: loop propagations (N for naive)          */
     double   t_submit, t_admit, t_done;  /* seconds, steady clock of the server           */
 } gapd_result;
 

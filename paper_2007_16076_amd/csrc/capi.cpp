@@ -178,7 +178,8 @@ int gapd_workspace_size(gapd_ctx *ctx, int mode, size_t *bytes) {
     if (st) return st;
     if (!bytes) return fail(ctx, GAPD_EINVAL, "bytes is null");
     if (mode == GAPD_MODE_NAIVE) { *bytes = 0; return GAPD_OK; }
-    if (mode != GAPD_MODE_TREE_FILL_FR) return fail(ctx, GAPD_EINVAL, "unknown mode");
+    if (mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA && mode != GAPD_MODE_TREE_FILL_SPIRAL)
+        return fail(ctx, GAPD_EINVAL, "unknown mode");
     *bytes = fr_workspace_bytes(ctx->N, true);
     return GAPD_OK;
 }
@@ -206,15 +207,15 @@ int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out) {
     return run_rows(ctx->g, sources, 0, K, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err, ctx->poisoned);
 }
 
-int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
-    int st = ctx_check(ctx);
-    if (st) return st;
-    if (!out) return fail(ctx, GAPD_EINVAL, "out is null");
-    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR) return fail(ctx, GAPD_EINVAL, "unknown mode");
+namespace {
+
+// One all-pairs call: the naive method (rule < 0) or a tree-based method.
+int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_t *out, gapd_stats *stp) {
     gapd_stats local{};
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    int st = GAPD_OK;
     hipEvent_t e0, e1, e2;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
@@ -224,7 +225,7 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
     } guard{e0, e1, e2};
     HIP_OR_FAIL(ctx, hipEventRecord(e0, ctx->stream));
-    if (mode == GAPD_MODE_NAIVE) {
+    if (rule < 0) {
         st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
                       ctx->poisoned, &s.rounds, &s.ms_kernel);
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
@@ -232,8 +233,14 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         s.n_prop = ctx->N;
     } else {
         const size_t need = fr_workspace_bytes(ctx->N, true);
-        if (!ctx->ws || ctx->ws_bytes < need) return fail(ctx, GAPD_ENOMEM, "filling-rate workspace missing or too small");
+        if (!ctx->ws || ctx->ws_bytes < need) return fail(ctx, GAPD_ENOMEM, "tree-method workspace missing or too small");
         FrState fs = fr_workspace_layout(ctx->ws, ctx->N, true);
+        fs.H = ctx->g.H;
+        fs.W = ctx->g.W;
+        fs.rule = rule;
+        fs.rep_h = h;
+        fs.draws = draws;
+        if (rule == kRuleSpiral) fs.cache = nullptr;  // no speculation on random draws
         fs.D = out;
         fs.seq_out = s.sources_out;
         fs.filled_out = s.filled_out;
@@ -246,17 +253,41 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = hc.n_prop;
-        s.n_prop_setup = 2;
         s.rounds = hc.rounds;
-        s.centroid = hc.centroid;
         s.n_prop_speculative = hc.spec_props;
         s.n_cache_hits = hc.spec_hits;
+        if (rule != kRuleSpiral) {
+            s.n_prop_setup = 2;
+            s.centroid = hc.centroid;
+        }
         float ms = 0;
         if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s.ms_setup = ms;
     }
     float ms = 0;
     if (hipEventElapsedTime(&ms, e0, e2) == hipSuccess) s.ms_total = ms;
     return st;
+}
+
+}  // namespace
+
+int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
+    int st = ctx_check(ctx);
+    if (st) return st;
+    if (!out) return fail(ctx, GAPD_EINVAL, "out is null");
+    if (mode == GAPD_MODE_TREE_FILL_SPIRAL)
+        return fail(ctx, GAPD_EINVAL, "the spiral methods take draws: use gapd_all_pairs_spiral");
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return fail(ctx, GAPD_EINVAL, "unknown mode");
+    const int rule = mode == GAPD_MODE_NAIVE ? -1 : mode == GAPD_MODE_TREE_FILL_FR ? kRuleFilling : kRuleExtrema;
+    return all_pairs_impl(ctx, rule, 0, nullptr, out, stp);
+}
+
+int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *out, gapd_stats *stp) {
+    int st = ctx_check(ctx);
+    if (st) return st;
+    if (!out || !draws) return fail(ctx, GAPD_EINVAL, "out or draws is null");
+    if (h < 0 || h > 65536) return fail(ctx, GAPD_EINVAL, "repulsion distance out of range");
+    return all_pairs_impl(ctx, kRuleSpiral, h, draws, out, stp);
 }
 
 void gapd_destroy(gapd_ctx *ctx) {
@@ -274,6 +305,9 @@ namespace gapd {
 
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
              hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel) {
+    // Launch errors are read with hipGetLastError: drop one that an earlier,
+    // unrelated call left pending so it is not taken for ours.
+    (void)hipGetLastError();
     hipEvent_t k0 = nullptr, k1 = nullptr;
     if (ms_kernel) {
         if (hipEventCreate(&k0) != hipSuccess || hipEventCreate(&k1) != hipSuccess) ms_kernel = nullptr;
@@ -309,12 +343,21 @@ int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream
         err = std::string(where) + ": " + hipGetErrorString(e);
         return GAPD_EDEVICE;
     };
+    (void)hipGetLastError();  // as in run_rows
     hipError_t e = hipMemsetAsync(fs.mask, 0, (size_t)N * fs.MW * 4, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(fs.ctl, 0, sizeof(FrCtl), stream);
-    if (e == hipSuccess) e = launch_fr_init(fs, stream);
-    if (e == hipSuccess) e = launch_fr_setup(g, fs, max_rounds, stream);
-    if (e == hipSuccess && setup_done) e = hipEventRecord(setup_done, stream);
-    if (e != hipSuccess) return bad(e, "filling-rate setup");
+    if (e != hipSuccess) return bad(e, "clearing the filled-pairs matrix");
+    e = hipMemsetAsync(fs.ctl, 0, sizeof(FrCtl), stream);
+    if (e != hipSuccess) return bad(e, "clearing the loop state");
+    e = launch_fr_init(fs, stream);
+    if (e != hipSuccess) return bad(e, "filling-rate init launch");
+    if (fs.rule != kRuleSpiral) {
+        e = launch_fr_setup(g, fs, max_rounds, stream);
+        if (e != hipSuccess) return bad(e, "centroid and extrema launch");
+    }
+    if (setup_done) {
+        e = hipEventRecord(setup_done, stream);
+        if (e != hipSuccess) return bad(e, "setup event");
+    }
     // The loop runs on the device: each step selects its own source, so the
     // host only enqueues steps in chunks and reads the done flag between them.
     const int chunk = std::max(1, env_int("GAPD_FR_CHUNK", 64));
@@ -378,7 +421,7 @@ BatchPlan plan_batch(const int32_t *H, const int32_t *W, int B, int C, int mode)
         p.img_off[b] = p.imgs_bytes; p.imgs_bytes += N * C;
         p.w_off[b] = p.w_bytes; p.w_bytes += weight_block_bytes(H[b], W[b]);
         p.fr_off[b] = p.fr_bytes;
-        if (mode == GAPD_MODE_TREE_FILL_FR) p.fr_bytes += fr_workspace_bytes((int)N);
+        if (mode != GAPD_MODE_NAIVE) p.fr_bytes += fr_workspace_bytes((int)N);
     }
     p.imgs_bytes = al256(p.imgs_bytes);
     p.desc_bytes = al256(sizeof(BImg) * B) + al256(sizeof(GImgW) * B) + al256(sizeof(int64_t) * B) +
@@ -394,7 +437,8 @@ extern "C" {
 int gapd_batched_workspace_size(const int32_t *H, const int32_t *W, int B, int C, int conn, int mode, size_t *bytes) {
     if (!H || !W || B < 0 || !bytes || C < 1) return GAPD_EINVAL;
     if (conn != 4 && conn != 8) return GAPD_EINVAL;
-    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR) return GAPD_EINVAL;
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return GAPD_EINVAL;
     for (int b = 0; b < B; ++b)
         if (H[b] < 1 || W[b] < 1 || H[b] > kMaxLine || W[b] > kMaxLine) return GAPD_EINVAL;
     *bytes = plan_batch(H, W, B, C, mode).total;
@@ -407,9 +451,11 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
     if (B < 0 || !H || !W || !out_offsets) return GAPD_EINVAL;
     if (B == 0) return GAPD_OK;
     if (!images_packed || !out || !workspace) return GAPD_EINVAL;
-    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR) return GAPD_EINVAL;
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return GAPD_EINVAL;
     if ((uintptr_t)workspace & 255) return GAPD_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
+    (void)hipGetLastError();  // as in run_rows
     BatchPlan p = plan_batch(H, W, B, C, mode);
     if (ws_bytes < p.total) return GAPD_ENOMEM;
     std::string why;
@@ -459,8 +505,11 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
         items += N;
         max_line = std::max(max_line, std::max(H[b], W[b]));
         const size_t l = (size_t)H[b] * x.Wp * 4;
-        if (mode == GAPD_MODE_TREE_FILL_FR) {
+        if (mode != GAPD_MODE_NAIVE) {
             x.fr = fr_workspace_layout(frbase + p.fr_off[b], N);
+            x.fr.H = H[b];
+            x.fr.W = W[b];
+            x.fr.rule = mode == GAPD_MODE_TREE_FILL_EXTREMA ? kRuleExtrema : kRuleFilling;
             x.fr.D = out + out_offsets[b];
             wbytes = std::max(wbytes, (size_t)(conn == 8 ? 4 : 2) * ((N + 1) / 2) * 4);
         }
@@ -475,7 +524,7 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
     if (e == hipSuccess) e = hipMemcpyAsync(ioff_dev, ioff.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(bimg_dev, bi.data(), sizeof(BImg) * B, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(ctl_dev, 0, sizeof(FrCtl), st);
-    if (e == hipSuccess && mode == GAPD_MODE_TREE_FILL_FR) e = hipMemsetAsync(frbase, 0, p.fr_bytes, st);
+    if (e == hipSuccess && mode != GAPD_MODE_NAIVE) e = hipMemsetAsync(frbase, 0, p.fr_bytes, st);
     if (e == hipSuccess) e = launch_prep_batched(gw_dev, imgs_dev, ioff_dev, B, C, weight_mode, st);
     if (e == hipSuccess) {
         if (mode == GAPD_MODE_NAIVE) {

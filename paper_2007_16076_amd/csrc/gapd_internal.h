@@ -63,15 +63,26 @@ struct FrCtl {
     int64_t filled;     // a: filled unordered pairs
     int64_t rounds;     // sweep rounds summed over propagations
     int32_t tree_slot;  // tree-cache slot holding the current source's tree, -1: the packed array
-    int32_t next_slot;  // round-robin cursor of the tree cache
     int32_t spec_n;     // candidates listed for speculation this step
     int32_t spec_hits;  // steps whose tree came from the cache
+    int32_t sp_turn1;   // spiral rules: current turn + 1 (0: none yet)
+    int32_t _pad;
     int64_t spec_props; // speculative propagations computed
 };
 
 // Device state of the filling-rate method for one image.
+// Source-selection rules of the tree-based methods.
+constexpr int kRuleFilling = 0;  // least filled, then greatest extremum (Section 3.4)
+constexpr int kRuleExtrema = 1;  // greatest extremum, then least filled (Section 3.3)
+constexpr int kRuleSpiral = 2;   // random in the outermost unfilled turn (Sections 3.1, 3.2)
+
 struct FrState {
     int N, MW;                 // pixels; 32-bit words per row of the filled-pairs matrix
+    int H, W;
+    int rule;                  // kRule*
+    int rep_h;                 // spiral: repulsion distance (<= 1: none)
+    const uint32_t *draws;     // spiral: N uniform 32-bit draws, one per selection
+    int32_t *sp_in;            // spiral: membership in S by position along the turn
     uint32_t *mask;            // N * MW bits: D_mrk
     int32_t *count;            // N: filled entries of each row (diagonal included)
     int32_t *rank;             // N: position in the decreasing geodesic-extrema list
@@ -80,7 +91,8 @@ struct FrState {
     uint32_t *full;            // ceil(N/32) words: bit i set once count[i] == N
     // Tree cache for speculative propagations (null when not used): kSpecSlots
     // trees of N words, the slot of each source (-1: none), the source of each
-    // slot (-1: empty) and the candidates listed by the current step.
+    // slot (-1: empty) and the current step's plan: kSpecK candidates, then
+    // the kSpecK slots they replace.
     uint32_t *cache;
     int32_t *src_slot;
     int32_t *slot_src;
@@ -96,8 +108,8 @@ struct FrState {
 // not cached; their propagations run beside the fill, into a cache of
 // kSpecSlots trees.  A tree depends on the image only, so a cached tree is
 // exactly the tree the step would compute.
-constexpr int kSpecK = 8;
-constexpr int kSpecSlots = 64;
+constexpr int kSpecK = 32;      // speculative propagations per filling-rate step, at most
+constexpr int kSpecSlots = 128; // trees kept in the cache (at most 256, a power of two)
 
 // Workspace layout of a single-image filling-rate run (spec: with the cache).
 size_t fr_workspace_bytes(int N, bool spec = false);

@@ -650,66 +650,245 @@ __global__ void k_rank_b(const BImg *imgs) {
 
 // Least filled point (Section 3.4): argmin over x of (count[x], rank[x]).
 // Returns the pixel, or -1 when that point is filled (D is complete).
+// Selection keys of the deterministic rules; the smaller key wins.
+//   filling rate (Section 3.4): count, then rank in the extrema list, 19 + 19
+//     bits.  A point whose row is complete keeps its key: the loop ends when
+//     the least key belongs to such a point.
+//   extrema (Section 3.3): distance from the centroid (greatest first), then
+//     count, then index, 27 + 18 + 18 bits.  Points whose rows are complete
+//     are left out (kNoKey).
+constexpr uint64_t kNoKey = ~0ull;
+constexpr uint64_t kDcMax = (1u << 27) - 1;
+
+template <int RULE>
+__device__ __forceinline__ const int32_t *sel_aux(const FrState &fs) {
+    return RULE == kRuleFilling ? fs.rank : fs.dbuf;
+}
+
+template <int RULE>
+__device__ __forceinline__ uint64_t sel_key(const FrState &fs, int x, int c, int aux) {
+    if (RULE == kRuleFilling) return ((uint64_t)(uint32_t)c << 19) | (uint32_t)aux;
+    if (c >= fs.N) return kNoKey;
+    return ((kDcMax - (uint32_t)aux) << 36) | ((uint64_t)(uint32_t)c << 18) | (uint32_t)x;
+}
+
+template <int RULE>
+__device__ __forceinline__ bool key_done(const FrState &fs, uint64_t k) {
+    return RULE == kRuleFilling ? (int)(k >> 19) >= fs.N : k == kNoKey;
+}
+
+template <int RULE>
+__device__ __forceinline__ int key_point(const FrState &fs, uint64_t k) {
+    return RULE == kRuleFilling ? fs.order[(int)(k & 0x7FFFFu)] : (int)(k & 0x3FFFFu);
+}
+
+// A coarser key of at most 46 bits that orders points the same way up to
+// ties (for the cache's eviction order, a heuristic).
+template <int RULE>
+__device__ __forceinline__ uint64_t key_heur(uint64_t k) {
+    return RULE == kRuleFilling ? k : k >> 18;
+}
+
+// The source of the step by a deterministic rule, -1 when D is filled.
+template <int RULE>
 __device__ int fr_select(const FrState &fs, uint64_t *red) {
     constexpr int U = 8;  // independent loads in flight per thread
-    uint64_t best = ~0ull;
+    const int32_t *aux = sel_aux<RULE>(fs);
+    uint64_t best = kNoKey;
     const int step = blockDim.x * U;
     for (int base = threadIdx.x; base < fs.N; base += step) {
-        int c[U], r[U];
+        int c[U], a[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int x = min(base + k * (int)blockDim.x, fs.N - 1);
             c[k] = fs.count[x];
-            r[k] = fs.rank[x];
+            a[k] = aux[x];
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const uint64_t key = ((uint64_t)(uint32_t)c[k] << 32) | (uint32_t)r[k];
+            const int x = min(base + k * (int)blockDim.x, fs.N - 1);
+            const uint64_t key = sel_key<RULE>(fs, x, c[k], a[k]);
             best = key < best ? key : best;  // clamped duplicates change nothing
         }
     }
     best = block_min_u64(best, red);
-    if ((int)(best >> 32) >= fs.N) return -1;
-    return fs.order[(int)(best & 0xFFFFFFFFu)];
+    if (key_done<RULE>(fs, best)) return -1;
+    return key_point<RULE>(fs, best);
 }
 
-// Ascending bitonic sort of 2 * blockDim.x keys in LDS (blockDim.x a power of two).
-__device__ void block_bitonic_sort(uint64_t *k) {
+// Block-wide exclusive prefix sum in thread order (red: one slot per wave).
+__device__ int block_excl_scan(int v, int64_t *red) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wave] = x;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += (int)red[w];
+    __syncthreads();
+    return base + x - v;
+}
+
+// Spiral turn k (Section 3.1): the frame of the pixels at distance k from
+// the image border, walked clockwise from its top-left corner (top row,
+// right column, bottom row, left column); a single row or column is walked
+// left to right or top to bottom.
+struct Turn {
+    int top, left, bottom, right, len;
+    bool cyclic;
+};
+
+__device__ __forceinline__ Turn turn_of(int H, int W, int k) {
+    Turn t{k, k, H - 1 - k, W - 1 - k, 0, false};
+    if (k < 0 || t.top > t.bottom || t.left > t.right) { t.len = 0; return t; }
+    const int h = t.bottom - t.top + 1, w = t.right - t.left + 1;
+    if (h == 1) t.len = w;
+    else if (w == 1) t.len = h;
+    else { t.len = 2 * (h + w) - 4; t.cyclic = true; }
+    return t;
+}
+
+__device__ __forceinline__ int turn_pixel(const Turn &t, int W, int p) {
+    const int h = t.bottom - t.top + 1, w = t.right - t.left + 1;
+    if (h == 1) return t.top * W + t.left + p;
+    if (w == 1) return (t.top + p) * W + t.left;
+    if (p < w) return t.top * W + t.left + p;
+    p -= w;
+    if (p < h - 1) return (t.top + 1 + p) * W + t.right;
+    p -= h - 1;
+    if (p < w - 1) return t.bottom * W + t.right - 1 - p;
+    p -= w - 1;
+    return (t.bottom - 1 - p) * W + t.left;
+}
+
+// Source of a spiral step (Sections 3.1 and 3.2): drop the filled points
+// from S; when S is empty, take the outermost turn that still has an
+// unfilled point and set S to its unfilled points; draw number n_prop picks
+// member floor(draw |S| / 2^32) of S in turn order; with repulsion h the
+// turn pixels 1 .. h-1 positions away on either side leave S.  -1 when D is
+// filled.
+__device__ int spiral_select(const FrState &fs, uint64_t *red) {
+    __shared__ int sh_pos;
+    FrCtl *ctl = fs.ctl;
+    const int N = fs.N, W = fs.W;
+    const int turn1 = ctl->sp_turn1;
+    const int64_t t = ctl->n_prop;
+    Turn tn = turn_of(fs.H, W, turn1 - 1);
+    int mine = 0;
+    for (int p = threadIdx.x; p < tn.len; p += blockDim.x) {
+        int in = fs.sp_in[p];
+        if (in && fs.count[turn_pixel(tn, W, p)] >= N) {
+            in = 0;
+            fs.sp_in[p] = 0;
+        }
+        mine += in;
+    }
+    int ns = (int)block_sum_i64(mine, (int64_t *)red);
+    if (ns == 0) {
+        uint64_t kb = kNoKey;
+        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+            if (fs.count[x] >= N) continue;
+            const int y = x / W, xx = x - y * W;
+            const int b = min(min(y, xx), min(fs.H - 1 - y, W - 1 - xx));
+            kb = (uint64_t)b < kb ? (uint64_t)b : kb;
+        }
+        kb = block_min_u64(kb, red);
+        if (kb == kNoKey) return -1;
+        tn = turn_of(fs.H, W, (int)kb);
+        mine = 0;
+        for (int p = threadIdx.x; p < tn.len; p += blockDim.x) {
+            const int in = fs.count[turn_pixel(tn, W, p)] < N;
+            fs.sp_in[p] = in;
+            mine += in;
+        }
+        ns = (int)block_sum_i64(mine, (int64_t *)red);
+        if (threadIdx.x == 0) ctl->sp_turn1 = (int)kb + 1;
+    }
+    const uint32_t r = t < N ? fs.draws[t] : 0u;
+    const int j = (int)(((uint64_t)r * (uint64_t)ns) >> 32);
+    // member j: each thread counts a contiguous run of positions
+    const int C = (tn.len + blockDim.x - 1) / blockDim.x;
+    const int p0 = min((int)threadIdx.x * C, tn.len), p1 = min(p0 + C, tn.len);
+    int cnt = 0;
+    for (int p = p0; p < p1; ++p) cnt += fs.sp_in[p];
+    if (threadIdx.x == 0) sh_pos = 0;
+    const int before = block_excl_scan(cnt, (int64_t *)red);
+    if (j >= before && j < before + cnt) {
+        int left = j - before, p = p0;
+        for (; p < p1 - 1; ++p)
+            if (fs.sp_in[p] && left-- == 0) break;
+        sh_pos = p;
+    }
+    __syncthreads();
+    const int pos = sh_pos;
+    if (threadIdx.x == 0) {
+        const int reach = min(fs.rep_h - 1, tn.len);
+        for (int d = 1; d <= reach; ++d)
+            for (int side = -1; side <= 1; side += 2) {
+                int p = pos + side * d;
+                if (tn.cyclic) p = ((p % tn.len) + tn.len) % tn.len;
+                else if (p < 0 || p >= tn.len) continue;
+                fs.sp_in[p] = 0;
+            }
+    }
+    return turn_pixel(tn, W, pos);
+}
+
+// Ascending bitonic sorts in LDS of a[0 .. 2 * blockDim.x) and, in the same
+// passes, of b[0 .. nb) (nb a power of two, at most 2 * blockDim.x; the
+// stages of the shorter sort are a prefix of those of the longer one).
+__device__ void block_bitonic_sort2(uint64_t *a, uint64_t *b, int nb) {
     const int n = 2 * blockDim.x, t = threadIdx.x;
     for (int size = 2; size <= n; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
             const int i = (t / stride) * 2 * stride + (t % stride), jj = i + stride;
             const bool up = (i & size) == 0;
-            const uint64_t a = k[i], b = k[jj];
-            if ((a > b) == up) { k[i] = b; k[jj] = a; }
+            const uint64_t x = a[i], y = a[jj];
+            if ((x > y) == up) { a[i] = y; a[jj] = x; }
+            if (size <= nb && jj < nb) {
+                const uint64_t u = b[i], v = b[jj];
+                if ((u > v) == up) { b[i] = v; b[jj] = u; }
+            }
         }
     __syncthreads();
 }
 
-// fr_select, and from the same pass the candidates for speculation: up to
-// kSpecK points other than the selected one, with the smallest keys among
-// points whose rows are incomplete and whose trees are not cached.  Each
-// thread keeps its two best such keys; the block sorts the 2 * blockDim.x of
-// them.  The list goes to fs.spec_list, its length to *n_cand.
-__device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, int *n_cand) {
+// fr_select, and from the same pass the speculation plan for this step.
+// Candidates: the points with the smallest keys other than the selected one,
+// among those whose rows are incomplete and whose trees are not cached (each
+// thread keeps its two best, the block sorts them).  Victims: the cache
+// slots in eviction order, free slots first, then slots whose source's row
+// is complete, then by decreasing key of their source; the slot holding the
+// selected point's tree is never a victim.  Candidate j replaces victim j
+// while its key is the smaller one.  The plan goes to fs.spec_list
+// (candidates, then victim slots), its length to *n_plan.
+template <int RULE>
+__device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, uint64_t *skeys, int *n_plan) {
     constexpr int U = 8;
-    constexpr uint64_t kNone = ~0ull;
-    uint64_t best = kNone, c1 = kNone, c2 = kNone;
+    constexpr uint64_t kTop = (1ull << 46) - 1;
+    const int32_t *aux = sel_aux<RULE>(fs);
+    uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
     const int step = blockDim.x * U;
     for (int base = threadIdx.x; base < fs.N; base += step) {
-        int c[U], r[U], sl[U];
+        int c[U], a[U], sl[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int x = min(base + k * (int)blockDim.x, fs.N - 1);
             c[k] = fs.count[x];
-            r[k] = fs.rank[x];
+            a[k] = aux[x];
             sl[k] = fs.src_slot[x];
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            if (base + k * (int)blockDim.x >= fs.N) continue;
-            const uint64_t key = ((uint64_t)(uint32_t)c[k] << 32) | (uint32_t)r[k];
+            const int x = base + k * (int)blockDim.x;
+            if (x >= fs.N) continue;
+            const uint64_t key = sel_key<RULE>(fs, x, c[k], a[k]);
             best = key < best ? key : best;
             if (sl[k] < 0 && c[k] < fs.N) {
                 if (key < c1) { c2 = c1; c1 = key; }
@@ -718,22 +897,40 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
         }
     }
     best = block_min_u64(best, red);
-    if (c1 == best) { c1 = c2; c2 = kNone; }
-    else if (c2 == best) c2 = kNone;
+    const int s = key_done<RULE>(fs, best) ? -1 : key_point<RULE>(fs, best);
+    if (c1 == best) { c1 = c2; c2 = kNoKey; }
+    else if (c2 == best) c2 = kNoKey;
     keys[2 * threadIdx.x] = c1;
     keys[2 * threadIdx.x + 1] = c2;
-    block_bitonic_sort(keys);
-    if (threadIdx.x < kSpecK) {
-        const uint64_t k = keys[threadIdx.x];
-        fs.spec_list[threadIdx.x] = k == kNone ? -1 : fs.order[(int)(k & 0xFFFFFFFFu)];
+    // eviction order: (keep value << 8) | slot, keep value 0 for a free slot,
+    // 1 for a complete row, 2 + (kTop - coarse key) otherwise, all ones when pinned
+    if (threadIdx.x < kSpecSlots) {
+        const int src = fs.slot_src[threadIdx.x];
+        uint64_t keep;
+        if (src < 0) keep = 0;
+        else if (src == s) keep = (1ull << 50) - 1;
+        else {
+            const int cs = fs.count[src];
+            keep = cs >= fs.N ? 1 : 2 + (kTop - key_heur<RULE>(sel_key<RULE>(fs, src, cs, aux[src])));
+        }
+        skeys[threadIdx.x] = (keep << 8) | (uint64_t)threadIdx.x;
     }
+    block_bitonic_sort2(keys, skeys, kSpecSlots);
+    if (threadIdx.x < kSpecK) {
+        const uint64_t ck = keys[threadIdx.x];
+        const uint64_t keep = skeys[threadIdx.x] >> 8;
+        const bool take = ck != kNoKey && (keep < 2 || key_heur<RULE>(ck) < kTop - (keep - 2));
+        fs.spec_list[threadIdx.x] = ck == kNoKey ? -1 : key_point<RULE>(fs, ck);
+        fs.spec_list[kSpecK + threadIdx.x] = (int)(skeys[threadIdx.x] & 0xFFu);
+        keys[kSpecK + threadIdx.x] = take ? 1 : 0;  // 'take' is monotone in j: a prefix
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         int n = 0;
-        while (n < kSpecK && keys[n] != kNone) ++n;
-        *n_cand = n;
+        while (n < kSpecK && keys[kSpecK + n]) ++n;
+        *n_plan = n;
     }
-    if ((int)(best >> 32) >= fs.N) return -1;
-    return fs.order[(int)(best & 0xFFFFFFFFu)];
+    return s;
 }
 
 // One step of the filling-rate loop: select s, propagate from s, write the
@@ -742,12 +939,19 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
 // counts the images of a batch whose loop has ended.
 template <int CONN, int S, bool kStageW, bool kSpec = false>
 __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, uint64_t *red,
-                              int *batch_done, uint64_t *keys = nullptr) {
+                              int *batch_done, uint64_t *keys = nullptr, uint64_t *skeys = nullptr) {
     FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     if (threadIdx.x == 0 && fs.filled_out && ctl->n_prop > 0) fs.filled_out[ctl->n_prop - 1] = ctl->filled;
     __shared__ int n_cand;
-    const int s = kSpec ? fr_select_spec(fs, red, keys, &n_cand) : fr_select(fs, red);
+    int s;
+    if (fs.rule == kRuleSpiral) {
+        s = spiral_select(fs, red);  // random draws: nothing to speculate on
+        if (kSpec && threadIdx.x == 0) n_cand = 0;
+    } else if (fs.rule == kRuleExtrema)
+        s = kSpec ? fr_select_spec<kRuleExtrema>(fs, red, keys, skeys, &n_cand) : fr_select<kRuleExtrema>(fs, red);
+    else
+        s = kSpec ? fr_select_spec<kRuleFilling>(fs, red, keys, skeys, &n_cand) : fr_select<kRuleFilling>(fs, red);
     if (s < 0) {
         if (threadIdx.x == 0) {
             ctl->done = 1;
@@ -805,12 +1009,16 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrSta
     fr_step_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, red, nullptr);
 }
 
+// Static LDS of the speculation plan's sort keys (beyond the usual reserve).
+constexpr size_t kSpecSortLds = (2 * kRelaxThreads + kSpecSlots) * sizeof(uint64_t);
+
 template <int CONN, int S, bool kStageW>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
     __shared__ uint64_t keys[2 * kRelaxThreads];
-    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys);
+    __shared__ uint64_t skeys[kSpecSlots];
+    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys);
 }
 
 // Every image of a batch takes its step at once: block b is image b.
@@ -956,27 +1164,18 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
 }
 
-// Propagation of one speculative candidate into a free slot of the tree cache
-// (never the slot this step's fill reads).  One block.
+// Propagation of speculative candidate j into its victim slot of the tree
+// cache (never the slot this step's fill reads).  One block.
 template <int CONN, int S, bool kStageW>
 __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, int j) {
     FrCtl *ctl = fs.ctl;
     if (j >= ctl->spec_n) return;
-    const int c = fs.spec_list[j];
-    if (c < 0) return;
-    __shared__ int sh_slot;
+    const int c = fs.spec_list[j], sl = fs.spec_list[kSpecK + j];
     if (threadIdx.x == 0) {
-        int sl;
-        do {
-            sl = atomicAdd(&ctl->next_slot, 1) % kSpecSlots;
-        } while (sl == ctl->tree_slot);
         const int old = fs.slot_src[sl];
         if (old >= 0) fs.src_slot[old] = -1;
         fs.slot_src[sl] = -1;
-        sh_slot = sl;
     }
-    __syncthreads();
-    const int sl = sh_slot;
     uint32_t *tree = fs.cache + (size_t)sl * fs.N;
     int *d = smem;
     NbW w = nbw_of(g);
@@ -1173,8 +1372,7 @@ struct FrStep {
 
     template <bool kStageW>
     static hipError_t launch_step(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
-                                  size_t lds) {
-        const bool spec = fs.cache && (size_t)g.N * sizeof(uint32_t) <= kMaxLds;
+                                  size_t lds, bool spec) {
         auto k1 = spec ? k_fr_step_spec<CONN, S, kStageW> : k_fr_step<CONN, S, kStageW>;
         hipError_t e = set_lds(k1, lds);
         if (e != hipSuccess) return e;
@@ -1186,16 +1384,21 @@ struct FrStep {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
-        hipError_t e = lds + wbytes <= kMaxLds ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes)
-                                               : launch_step<false>(g, Wp, fs, max_rounds, st, lds);
+        const size_t pk = (size_t)g.N * sizeof(uint32_t);
+        // speculation needs the fill to stage a tree in LDS and the select
+        // kernel to hold its sort keys beside the field
+        const bool spec = fs.cache && pk <= kMaxLds && lds + kSpecSortLds <= kMaxLds;
+        const size_t extra = spec ? kSpecSortLds : 0;
+        hipError_t e = lds + wbytes + extra <= kMaxLds
+                           ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes, spec)
+                           : launch_step<false>(g, Wp, fs, max_rounds, st, lds, spec);
         if (e != hipSuccess) return e;
         if (mid) {
             e = hipEventRecord(mid, st);
             if (e != hipSuccess) return e;
         }
-        const size_t pk = (size_t)g.N * sizeof(uint32_t);
         const int blocks = (g.N + 255) / 256;
-        if (fs.cache && pk <= kMaxLds) {
+        if (spec) {
             // the fill beside the speculative propagations
             const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
             if (2 * pk <= kMaxLds) {
@@ -1312,9 +1515,9 @@ GImgW weight_block_layout(void *dev, int H, int W, int conn) {
 
 size_t fr_workspace_bytes(int N, bool spec) {
     const size_t MW = ((size_t)N + 31) / 32;
-    size_t b = al256((size_t)N * MW * 4) + 6 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
+    size_t b = al256((size_t)N * MW * 4) + 7 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
     if (spec)
-        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + al256(kSpecSlots * 4) + al256(kSpecK * 4);
+        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + al256(kSpecSlots * 4) + al256(2 * kSpecK * 4);
     return b;
 }
 
@@ -1330,6 +1533,7 @@ FrState fr_workspace_layout(void *ws, int N, bool spec) {
     f.packed = (uint32_t *)p; p += al256((size_t)N * 4);
     f.dbuf = (int32_t *)p; p += al256((size_t)N * 4);
     f.full = (uint32_t *)p; p += al256((size_t)N * 4);
+    f.sp_in = (int32_t *)p; p += al256((size_t)N * 4);  // a spiral turn has at most N pixels
     f.ctl = (FrCtl *)p; p += al256(sizeof(FrCtl));
     if (spec) {
         f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * N * 4);

@@ -90,7 +90,7 @@ size_t job_bytes(const gapd_job &j, size_t *elems) {
     const size_t N = (size_t)j.H * j.W;
     size_t b = al256(N * j.C) + weight_block_bytes(j.H, j.W) + al256(sizeof(FrCtl));
     if (j.kind == GAPD_JOB_ALL_PAIRS) {
-        if (j.mode == GAPD_MODE_TREE_FILL_FR) b += fr_workspace_bytes((int)N, true);
+        if (j.mode != GAPD_MODE_NAIVE) b += fr_workspace_bytes((int)N, true);
         *elems = N * N;
     } else {
         b += al256(sizeof(int32_t) * (size_t)j.K);
@@ -142,9 +142,12 @@ int gapd_server::run_job(JobRec &j, hipStream_t st) {
     const GImg g = as_const(w);
     const int max_rounds = max_rounds_for(N);
     if (s.kind == GAPD_JOB_ALL_PAIRS) {
-        if (s.mode == GAPD_MODE_TREE_FILL_FR) {
+        if (s.mode != GAPD_MODE_NAIVE) {
             FrState fs = fr_workspace_layout(p, N, true);
             p += fr_workspace_bytes(N, true);
+            fs.H = s.H;
+            fs.W = s.W;
+            fs.rule = s.mode == GAPD_MODE_TREE_FILL_EXTREMA ? kRuleExtrema : kRuleFilling;
             fs.D = (int32_t *)p;
             j.dev_out = fs.D;
             FrCtl hc{};
@@ -230,9 +233,11 @@ int gapd_serve_submit(gapd_server *srv, const gapd_job *job, uint64_t *ticket) {
     if (st != GAPD_OK) { g_create_error = why; return st; }
     const int N = job->H * job->W;
     if (job->kind == GAPD_JOB_ALL_PAIRS) {
-        if (job->mode != GAPD_MODE_NAIVE && job->mode != GAPD_MODE_TREE_FILL_FR) return GAPD_EINVAL;
+        if (job->mode != GAPD_MODE_NAIVE && job->mode != GAPD_MODE_TREE_FILL_FR &&
+            job->mode != GAPD_MODE_TREE_FILL_EXTREMA)
+            return GAPD_EINVAL;
         const size_t lds = (size_t)job->H * lds_row_stride(job->W) * 4;
-        if (job->mode == GAPD_MODE_TREE_FILL_FR && lds > kMaxLds) {
+        if (job->mode != GAPD_MODE_NAIVE && lds > kMaxLds) {
             g_create_error = "filling-rate jobs need the distance field to fit in LDS";
             return GAPD_EINVAL;
         }

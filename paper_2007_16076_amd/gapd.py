@@ -19,12 +19,12 @@ LIB_PATH = os.path.join(HERE, "libgapd.so")
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ERANGE, ENOCONV, EBUSY, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6, -7
 CONN4, CONN8 = 4, 8
 W_SUM, W_1PL1 = 0, 1
-MODE_NAIVE, MODE_TREE_FILL_FR = 0, 1
+MODE_NAIVE, MODE_TREE_FILL_FR, MODE_TREE_FILL_EXTREMA, MODE_TREE_FILL_SPIRAL = 0, 1, 2, 3
 JOB_ALL_PAIRS, JOB_MULTI_SOURCE = 0, 1
 
 EXPORTED = [
     "gapd_create", "gapd_set_stream", "gapd_workspace_size", "gapd_set_workspace", "gapd_sssp",
-    "gapd_all_pairs", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
+    "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
     "gapd_all_pairs_batched", "gapd_server_create", "gapd_serve_submit", "gapd_serve_poll", "gapd_serve_wait",
     "gapd_serve_release", "gapd_server_destroy",
 ]
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "gapd_set_workspace": ([P, P, SZ], I),
         "gapd_sssp": ([P, P, I, P], I),
         "gapd_all_pairs": ([P, I, P, ctypes.POINTER(Stats)], I),
+        "gapd_all_pairs_spiral": ([P, I, P, P, ctypes.POINTER(Stats)], I),
         "gapd_destroy": ([P], None),
         "gapd_strerror": ([I], ctypes.c_char_p),
         "gapd_last_error": ([P], ctypes.c_char_p),
@@ -209,9 +210,34 @@ class Context:
         st.filled_out = _dptr(filled_out) if filled_out is not None else None
         st.time_kernels = 1 if time_kernels else 0
         _check(load_library().gapd_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
-        return out, AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup,
-                                  st.ms_kernel, st.ms_step_kernels, st.ms_fill_kernels, st.n_prop_speculative,
-                                  st.n_cache_hits)
+        return out, _stats(st)
+
+    def all_pairs_spiral(self, draws, h: int = 0, out=None, sources_out=None, filled_out=None,
+                         time_kernels: bool = False):
+        """The spiral method (h <= 1) or the spiral method with repulsion h (the
+        paper's is 3).  draws: N uniform uint32 (any array; copied to the device)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.int32, device="cuda")
+        d = draws if isinstance(draws, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(draws, dtype=np.uint32).view(np.int32))
+        d = d.to(device="cuda").contiguous()
+        if d.numel() < self.N or d.element_size() != 4:
+            raise ValueError("draws must hold N 32-bit values")
+        self._ensure_workspace(MODE_TREE_FILL_SPIRAL)
+        st = Stats()
+        st.sources_out = _dptr(sources_out) if sources_out is not None else None
+        st.filled_out = _dptr(filled_out) if filled_out is not None else None
+        st.time_kernels = 1 if time_kernels else 0
+        _check(load_library().gapd_all_pairs_spiral(self._h, int(h), _dptr(d), _dptr(out), ctypes.byref(st)),
+               self._h)
+        return out, _stats(st)
+
+
+def _stats(st) -> "AllPairsStats":
+    return AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup,
+                         st.ms_kernel, st.ms_step_kernels, st.ms_fill_kernels, st.n_prop_speculative,
+                         st.n_cache_hits)
 
 
 def batched_workspace_size(shapes, C: int = 1, conn: int = CONN4, mode: int = MODE_NAIVE) -> int:
