@@ -14,6 +14,13 @@ available):
   batched    256 iid images of sides 24..96 in one call, both methods
   serve      Poisson request stream through the continuous-batching server
   hbmcopy    a plain 1 GiB device copy (calibrates rocprofv3's byte counters)
+  blob128c8  the 128x128 blob image with 8-neighbours, filling-rate vs naive
+  deltar     the paper's method comparison (Sections 3 and 4): propagations
+             to fill D for naive, spiral, spiral with repulsion 3, geodesic
+             extrema and filling rate, 8-neighbours, on 25x25 stand-ins for
+             "random", "bumps" and "hairpin bend" (spiral methods averaged
+             over --draw-seeds draw sequences), with filling-rate curves;
+             then every tree method timed once on the 128x128 blob image
 
 Prints ONE JSON line.  Inputs are resident on the GPU when the timed region
 starts; the timed region is bracketed by torch.cuda.synchronize().
@@ -346,13 +353,92 @@ def hbmcopy_line(args):
             "data": "synthetic", "config": {"workload": "hbmcopy", "bytes_read": 4 * n, "bytes_written": 4 * n}}
 
 
+def deltar_line(args):
+    """Propagation counts and relative differences of the tree methods (the
+    comparison of Sections 3 and 4), all computed by the GPU library."""
+    import torch
+    import synth
+    from paper_2007_16076_amd import gapd
+    conn = 8
+    out = {}
+    t0 = time.time()
+
+    def run(ctx, mode=None, draws=None, h=0):
+        N = ctx.N
+        fil = torch.zeros(N, dtype=torch.int64, device="cuda")
+        if draws is None:
+            _, st = ctx.all_pairs(mode, filled_out=fil)
+        else:
+            _, st = ctx.all_pairs_spiral(draws, h=h, filled_out=fil)
+        torch.cuda.synchronize()
+        return st, fil.cpu().numpy()[:st.n_prop]
+
+    for name, img in synth.deltar_images().items():
+        N = img.size
+        A = N * (N - 1) // 2
+        ctx = gapd.Context(img, conn=conn)
+        res = {}
+        curves = {}
+        for mname, mode in (("filling_rate", gapd.MODE_TREE_FILL_FR), ("extrema", gapd.MODE_TREE_FILL_EXTREMA)):
+            st, fil = run(ctx, mode=mode)
+            res[mname] = {"n_prop": int(st.n_prop), "n_prop_plus_setup": int(st.n_prop + st.n_prop_setup)}
+            curves[mname] = fil
+        for mname, h in (("spiral", 0), ("spiral_repulsion3", 3)):
+            ns = []
+            for sd in range(args.draw_seeds):
+                st, fil = run(ctx, draws=synth.spiral_draws(sd, N), h=h)
+                ns.append(int(st.n_prop))
+                if sd == 0:
+                    curves[mname] = fil
+            res[mname] = {"n_prop_mean": float(np.mean(ns)), "n_prop_std": round(float(np.std(ns)), 2),
+                          "n_prop_min": min(ns), "n_prop_max": max(ns), "draw_seeds": args.draw_seeds}
+        n_sp = res["spiral"]["n_prop_mean"]
+        for mname, r in res.items():
+            n = r.get("n_prop_mean", r.get("n_prop"))
+            r["dr_naive_pct"] = round(100.0 * (N - n) / N, 1)
+            r["dr_spiral_pct"] = round(100.0 * (n_sp - n) / n_sp, 1)
+            if "n_prop_plus_setup" in r:
+                r["dr_naive_plus_setup_pct"] = round(100.0 * (N - r["n_prop_plus_setup"]) / N, 1)
+                r["dr_spiral_plus_setup_pct"] = round(100.0 * (n_sp - r["n_prop_plus_setup"]) / n_sp, 1)
+        # filling rate tau = a / A after 10 %, 25 %, 50 % and 75 % of N propagations
+        tau = {m: {f"{q}%": round(float(c[min(len(c), max(1, int(q * N / 100))) - 1]) / A, 4) for q in (10, 25, 50, 75)}
+               for m, c in curves.items()}
+        out[name] = {"N": N, "sha256": synth.sha256(img), "naive_n_prop": N, "methods": res, "tau_at_naive_fraction": tau}
+        ctx.close()
+        log(f"[deltar] {name}: " + ", ".join(f"{m} {r.get('n_prop_mean', r.get('n_prop'))}" for m, r in res.items()))
+    # every tree method once on the 128x128 blob image (4-neighbours)
+    img = synth.config2()
+    ctx = gapd.Context(img, conn=4)
+    big = {}
+    for mname, kw in (("filling_rate", {"mode": gapd.MODE_TREE_FILL_FR}),
+                      ("extrema", {"mode": gapd.MODE_TREE_FILL_EXTREMA}),
+                      ("spiral", {"draws": synth.spiral_draws(0, img.size), "h": 0}),
+                      ("spiral_repulsion3", {"draws": synth.spiral_draws(0, img.size), "h": 3})):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, _ = run(ctx, **kw)
+        ms = (time.perf_counter() - t1) * 1e3
+        big[mname] = {"n_prop": int(st.n_prop), "ms": round(ms, 1), "cache_hits": int(st.n_cache_hits)}
+        log(f"[deltar] blob128 {mname}: n_prop {st.n_prop}, {ms:.0f} ms")
+    wall = time.time() - t0
+    return {"metric": "propagations to fill D, relative difference vs naive and spiral (Delta_r)",
+            "value": out["bumps"]["methods"]["filling_rate"]["dr_naive_pct"], "unit": "% (bumps, filling rate)",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic", "config": {"workload": "deltar", "side": 25, "conn": conn,
+                                            "weights": "f(p)+f(q)", "images": "synth.deltar_images(seed=7)"},
+            "images": out, "blob128_all_methods": big}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="blob128",
-                    choices=["blob128", "uniform32", "voronoi192", "batched", "serve", "hbmcopy"])
+                    choices=["blob128", "uniform32", "voronoi192", "batched", "serve", "hbmcopy", "blob128c8",
+                             "deltar"])
+    ap.add_argument("--draw-seeds", type=int, default=10, help="deltar: draw sequences per spiral method")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=30.0)
@@ -389,6 +475,15 @@ def main():
                                      "weights": "1 + L1 over 8 bands"})
         if not args.no_cpu_baseline:
             line["cpu_baseline"] = cpu_baseline_fr(img, 4, line["n_prop"], args.cpu_seconds)
+    elif args.workload == "blob128c8":
+        img = synth.config2()
+        line, _ = single_image_line(args, "blob128c8", img, 8,
+                                    {"image": "128x128 sum of 20 Gaussian blobs + noise, seed 1",
+                                     "weights": "f(p)+f(q)", "sha256": synth.sha256(img)})
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline_fr(img, 8, line["n_prop"], args.cpu_seconds)
+    elif args.workload == "deltar":
+        line = deltar_line(args)
     elif args.workload == "batched":
         line = batched_line(args)
     elif args.workload == "hbmcopy":

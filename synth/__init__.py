@@ -27,6 +27,9 @@ __all__ = [
     "uniform_image",
     "blob_image",
     "voronoi_image",
+    "hairpin_image",
+    "deltar_images",
+    "spiral_draws",
     "config1",
     "config2",
     "config3",
@@ -66,6 +69,46 @@ def blob_image(rng: np.random.Generator, h: int, w: int, n_blobs: int = 20,
     img = np.rint(img).astype(np.int64)
     img += rng.integers(-noise, noise + 1, size=(h, w))
     return np.ascontiguousarray(np.clip(img, 1, 255).astype(np.uint8))
+
+
+def hairpin_image(rng: np.random.Generator, h: int = 25, w: int = 25, half_width: float = 1.2,
+                  channel=(10, 30), background=(150, 250)) -> np.ndarray:
+    """A dark hairpin-shaped channel on a bright noisy background, uint8 (h, w).
+
+    The channel's centre line runs up the left leg (x = 0.3 w, from y = 0.9 h
+    to y = 0.4 h), over a half circle of radius 0.2 w centred at (0.4 h, 0.5 w),
+    and down the right leg (x = 0.7 w) to y = 0.9 h.  Pixels within
+    ``half_width`` of the centre line draw iid values in ``channel``, the others
+    in ``background`` (both inclusive).  With the sum-of-grey-levels metric the
+    cheap paths follow the bend.
+    """
+    yy, xx = np.meshgrid(np.arange(h, dtype=np.float64), np.arange(w, dtype=np.float64), indexing="ij")
+    cy, cx, r = 0.4 * h, 0.5 * w, 0.2 * w
+    y0, y1 = 0.4 * h, 0.9 * h
+    def leg(x0):
+        dy = np.where(yy < y0, y0 - yy, np.where(yy > y1, yy - y1, 0.0))
+        return np.hypot(xx - x0, dy)
+    ring = np.abs(np.hypot(yy - cy, xx - cx) - r)
+    ring = np.where(yy <= cy, ring, np.inf)  # the upper half circle only
+    dist = np.minimum(np.minimum(leg(cx - r), leg(cx + r)), ring)
+    lo = rng.integers(channel[0], channel[1] + 1, size=(h, w))
+    hi = rng.integers(background[0], background[1] + 1, size=(h, w))
+    return np.ascontiguousarray(np.where(dist <= half_width, lo, hi).astype(np.uint8))
+
+
+def deltar_images(seed: int = 7, side: int = 25) -> dict:
+    """Stand-ins for the paper's three side x side comparison images (Section 3):
+    "random" (iid 1..255), "bumps" (6 Gaussian blobs of width 2..6 px on the
+    blob generator) and "hairpin" (hairpin_image)."""
+    rng = np.random.default_rng(seed)
+    return {"random": uniform_image(rng, side, side),
+            "bumps": blob_image(rng, side, side, n_blobs=6, sigma=(2.0, 6.0), amp=(60.0, 200.0), noise=5),
+            "hairpin": hairpin_image(rng, side, side)}
+
+
+def spiral_draws(seed: int, n: int) -> np.ndarray:
+    """n uniform 32-bit draws for the spiral methods' random selections."""
+    return np.random.default_rng(seed).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
 
 
 def voronoi_image(rng: np.random.Generator, h: int, w: int, bands: int = 8, n_seeds: int = 50,

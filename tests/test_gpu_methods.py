@@ -191,3 +191,19 @@ def test_server_extrema_job(G, torch_mod, oracle_lib):
     assert r.n_prop == ref.n_prop
     srv.release(t)
     srv.close()
+
+
+@pytest.mark.parametrize("name", ["random", "bumps", "hairpin"])
+def test_comparison_images_all_methods(G, torch_mod, oracle_lib, name):
+    """The 25x25 stand-ins of the method comparison, 8-neighbours: every tree
+    method on the GPU gives the oracle's sequence and D."""
+    import synth
+    img = synth.deltar_images()[name]
+    N = img.size
+    say("comparison image", name)
+    check_same(run_method(G, torch_mod, img, 8, mode=G.MODE_TREE_FILL_FR), oracle_lib.filling_rate(img, conn=8), N)
+    check_same(run_method(G, torch_mod, img, 8, mode=G.MODE_TREE_FILL_EXTREMA),
+               oracle_lib.extrema_method(img, conn=8), N)
+    r = synth.spiral_draws(0, N)
+    for h in (0, 3):
+        check_same(run_method(G, torch_mod, img, 8, draws=r, h=h), oracle_lib.spiral(img, r, h=h, conn=8), N)
