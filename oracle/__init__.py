@@ -6,7 +6,8 @@ computation of all pairs of geodesic distances"): Dijkstra propagations,
 Floyd-Warshall for tiny images, the naive method, the geodesic centroid and
 extrema list, the filling-rate method with its redundancy fill, and with the
 same fill the geodesic extrema method and the spiral methods (with their
-random draws passed in).
+random draws passed in), and the propagation, fill and deterministic
+selection rules on general graphs in CSR form.
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import it.  It shares no code with the GPU library and never imports it;
@@ -65,6 +66,12 @@ def _load():
             "gapd_oracle_extrema_method": [P, i32, i32, i32, i32, i32, P, P, P, P, P, i64],
             "gapd_oracle_spiral": [P, i32, i32, i32, i32, i32, i32, P, i64, P, P, P, P, i64],
             "gapd_oracle_spiral_turn": [i32, i32, i32, P, P],
+            "gapd_oracle_graph_boundary": [i64, P, P],
+            "gapd_oracle_graph_dijkstra": [i64, P, P, P, P, i64, P],
+            "gapd_oracle_graph_parents": [i64, P, P, P, P, P],
+            "gapd_oracle_graph_rows": [i64, P, P, P, P, i64, P, i32],
+            "gapd_oracle_graph_extrema": [i64, P, P, P, P, P, P, P, P],
+            "gapd_oracle_graph_tree_method": [i64, P, P, P, P, i32, P, P, P, P, P, P, i64],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -252,3 +259,86 @@ def spiral_turn(H: int, W: int, k: int):
     cyc = np.zeros(1, dtype=np.int32)
     n = _load().gapd_oracle_spiral_turn(H, W, k, _ptr(out), _ptr(cyc))
     return out[:n].copy(), bool(cyc[0])
+
+
+# ---- general graphs (CSR) ------------------------------------------------------------------
+
+def _csr(rp, ci, cw):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    cw = np.ascontiguousarray(cw, dtype=np.int32)
+    return rp.size - 1, rp, ci, cw
+
+
+def _bnd(b):
+    return None if b is None else np.ascontiguousarray(b, dtype=np.uint8)
+
+
+def graph_boundary(rp) -> np.ndarray:
+    """Boundary flags by the degree rule (degree below the average; all if none)."""
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    out = np.zeros(rp.size - 1, dtype=np.uint8)
+    _check(_load().gapd_oracle_graph_boundary(rp.size - 1, _ptr(rp), _ptr(out)), "graph_boundary")
+    return out
+
+
+def graph_dijkstra(rp, ci, cw, seeds) -> np.ndarray:
+    n, rp, ci, cw = _csr(rp, ci, cw)
+    seeds = np.ascontiguousarray(np.atleast_1d(seeds), dtype=np.int64)
+    out = np.empty(n, dtype=np.int64)
+    _check(_load().gapd_oracle_graph_dijkstra(n, _ptr(rp), _ptr(ci), _ptr(cw), _ptr(seeds), seeds.size, _ptr(out)),
+           "graph_dijkstra")
+    return out
+
+
+def graph_parents(rp, ci, cw, dist) -> np.ndarray:
+    n, rp, ci, cw = _csr(rp, ci, cw)
+    dist = np.ascontiguousarray(dist, dtype=np.int64)
+    out = np.empty(n, dtype=np.int32)
+    _check(_load().gapd_oracle_graph_parents(n, _ptr(rp), _ptr(ci), _ptr(cw), _ptr(dist), _ptr(out)),
+           "graph_parents")
+    return out
+
+
+def graph_rows(rp, ci, cw, sources, threads=None) -> np.ndarray:
+    n, rp, ci, cw = _csr(rp, ci, cw)
+    src = np.ascontiguousarray(np.atleast_1d(sources), dtype=np.int32)
+    out = np.empty((src.size, n), dtype=np.int32)
+    _check(_load().gapd_oracle_graph_rows(n, _ptr(rp), _ptr(ci), _ptr(cw), _ptr(src), src.size, _ptr(out),
+                                          threads or os.cpu_count() or 1), "graph_rows")
+    return out
+
+
+def graph_naive(rp, ci, cw, threads=None) -> np.ndarray:
+    n = np.asarray(rp).size - 1
+    return graph_rows(rp, ci, cw, np.arange(n, dtype=np.int32), threads)
+
+
+def graph_extrema(rp, ci, cw, boundary=None) -> Extrema:
+    n, rp, ci, cw = _csr(rp, ci, cw)
+    b = _bnd(boundary)
+    c = np.zeros(1, dtype=np.int32)
+    de = np.empty(n, dtype=np.int64)
+    dc = np.empty(n, dtype=np.int64)
+    rk = np.empty(n, dtype=np.int32)
+    _check(_load().gapd_oracle_graph_extrema(n, _ptr(rp), _ptr(ci), _ptr(cw), None if b is None else _ptr(b),
+                                             _ptr(c), _ptr(de), _ptr(dc), _ptr(rk)), "graph_extrema")
+    return Extrema(int(c[0]), de, dc, rk)
+
+
+def graph_tree_method(rp, ci, cw, rule: int = 0, boundary=None, max_steps: int = -1) -> FillingRate:
+    """rule 0: filling rate; rule 1: geodesic extrema method."""
+    n, rp, ci, cw = _csr(rp, ci, cw)
+    b = _bnd(boundary)
+    D = np.full((n, n), -1, dtype=np.int32)
+    seq = np.full(n, -1, dtype=np.int32)
+    a = np.zeros(n, dtype=np.int64)
+    k = np.zeros(1, dtype=np.int64)
+    c = np.zeros(1, dtype=np.int32)
+    rk = np.empty(n, dtype=np.int32)
+    st = _check(_load().gapd_oracle_graph_tree_method(n, _ptr(rp), _ptr(ci), _ptr(cw),
+                                                      None if b is None else _ptr(b), int(rule), _ptr(D),
+                                                      _ptr(seq), _ptr(a), _ptr(k), _ptr(c), _ptr(rk),
+                                                      int(max_steps)), "graph_tree_method")
+    m = int(k[0])
+    return FillingRate(D, seq[:m].copy(), a[:m].copy(), m, int(c[0]), rk, st == TRUNCATED)

@@ -23,7 +23,10 @@
  *     (Section 2, Property 1);
  *   - with the same fill, the geodesic extrema method (Section 3.3,
  *     algorithm "extrema") and the spiral methods without and with repulsion
- *     (Sections 3.1 and 3.2), whose random draws are inputs.
+ *     (Sections 3.1 and 3.2), whose random draws are inputs;
+ *   - the same propagation, tree, fill and selection rules on a general
+ *     undirected graph in CSR form, whose boundary vertices replace the image
+ *     border (Section 5).
  *
  * Readings of the paper taken here (where it is silent or ambiguous):
  *   - pixel index i = y*W + x; no wrap-around at the image border;
@@ -45,7 +48,11 @@
  *     draw r (uniform 32 bits) picks member floor(r |S| / 2^32) of S in that
  *     order; repulsion h removes from S the turn pixels 1 .. h-1 positions
  *     away from s on either side (cyclically on a closed frame); a point is
- *     "filled" when its row of D is complete.
+ *     "filled" when its row of D is complete;
+ *   - general graphs: the boundary vertices are given, or by the example rule
+ *     of Section 5 the vertices of degree below the average (all vertices
+ *     when none is); weights are given per edge, symmetric, >= 1; the graph
+ *     must be connected.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -67,10 +74,17 @@
 #define ORACLE_MUTANT 0
 #endif
 
+/* The graph of a propagation: a pixel grid (img != NULL) or a general
+ * undirected graph in CSR form (rp != NULL; the generalisation of Section 5). */
 typedef struct {
     const uint8_t *img; /* H*W*C bytes, HWC row-major */
     int H, W, C, conn, wmode;
+    const int64_t *rp;  /* CSR: row pointers (N+1) */
+    const int32_t *ci;  /* CSR: neighbour ids */
+    const int32_t *cw;  /* CSR: edge weights (>= 1) */
+    const uint8_t *bnd; /* CSR: boundary flags (N) */
     int64_t N;
+    int64_t maxdeg;
 } or_graph;
 
 static int or_check(const or_graph *g) {
@@ -96,18 +110,38 @@ static int64_t or_weight(const or_graph *g, int64_t p, int64_t q) {
     return s;
 }
 
-/* Neighbours of p (Section 2, eqs. voisinage_1/2) in ascending index order. */
-static int or_neighbours(const or_graph *g, int64_t p, int64_t *out) {
-    int y = (int)(p / g->W), x = (int)(p % g->W), n = 0;
+/* Neighbours of p and the weights of the edges to them.  Pixel grid: the
+ * 4- or 8-neighbours (Section 2, eqs. voisinage_1/2) in ascending index order;
+ * CSR graph: the row of p as given.  out and wout hold g->maxdeg entries. */
+static int64_t or_neighbours(const or_graph *g, int64_t p, int64_t *out, int64_t *wout) {
+    int64_t n = 0;
+    if (g->rp) {
+        for (int64_t e = g->rp[p]; e < g->rp[p + 1]; ++e) {
+            out[n] = g->ci[e];
+            wout[n++] = g->cw[e];
+        }
+        return n;
+    }
+    int y = (int)(p / g->W), x = (int)(p % g->W);
     for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
             if (dy == 0 && dx == 0) continue;
             if (g->conn == 4 && dy != 0 && dx != 0) continue;
             int yy = y + dy, xx = x + dx;
             if (yy < 0 || yy >= g->H || xx < 0 || xx >= g->W) continue;
-            out[n++] = (int64_t)yy * g->W + xx;
+            out[n] = (int64_t)yy * g->W + xx;
+            wout[n] = or_weight(g, p, out[n]);
+            ++n;
         }
     return n;
+}
+
+/* Boundary vertices: the image border pixels (Section 3.3), or the flags of
+ * a CSR graph (Section 5). */
+static int or_is_boundary(const or_graph *g, int64_t p) {
+    if (g->rp) return g->bnd[p] != 0;
+    int y = (int)(p / g->W), x = (int)(p % g->W);
+    return y == 0 || (y == g->H - 1 && ORACLE_MUTANT != 7) || x == 0 || x == g->W - 1;
 }
 
 /* ---- binary heap of (distance, node), lazy deletion ---------------------------------- */
@@ -159,26 +193,30 @@ static int or_dijkstra(const or_graph *g, const int64_t *seeds, int64_t nseeds, 
         dist[seeds[k]] = 0;
         if (or_push(&h, 0, seeds[k])) { free(h.a); return OR_ENOMEM; }
     }
-    int64_t nb[8];
+    int64_t *nb = (int64_t *)malloc((size_t)(2 * g->maxdeg + 2) * sizeof(int64_t)), *wb = nb + g->maxdeg + 1;
+    if (!nb) { free(h.a); return OR_ENOMEM; }
     while (h.n > 0) {
         or_item it = or_pop(&h);
         if (it.d != dist[it.v]) continue; /* stale entry */
-        int k = or_neighbours(g, it.v, nb);
-        for (int j = 0; j < k; ++j) {
-            int64_t nd = it.d + or_weight(g, it.v, nb[j]);
+        int64_t k = or_neighbours(g, it.v, nb, wb);
+        for (int64_t j = 0; j < k; ++j) {
+            int64_t nd = it.d + wb[j];
             if (nd < dist[nb[j]]) {
                 dist[nb[j]] = nd;
-                if (or_push(&h, nd, nb[j])) { free(h.a); return OR_ENOMEM; }
+                if (or_push(&h, nd, nb[j])) { free(h.a); free(nb); return OR_ENOMEM; }
             }
         }
     }
     free(h.a);
+    free(nb);
     return OR_OK;
 }
 
 static int or_graph_init(or_graph *g, const uint8_t *img, int H, int W, int C, int conn, int wmode) {
+    memset(g, 0, sizeof(*g));
     g->img = img; g->H = H; g->W = W; g->C = C; g->conn = conn; g->wmode = wmode;
     g->N = (int64_t)H * W;
+    g->maxdeg = 8;
     return or_check(g);
 }
 
@@ -203,11 +241,11 @@ int gapd_oracle_floyd(const uint8_t *img, int H, int W, int C, int conn, int wmo
     if (!D || g.N > 1024) return OR_EINVAL;
     const int64_t N = g.N, INF = INT64_MAX / 4;
     for (int64_t i = 0; i < N * N; ++i) D[i] = INF;
-    int64_t nb[8];
+    int64_t nb[8], wb[8];
     for (int64_t p = 0; p < N; ++p) {
         D[p * N + p] = 0;
-        int k = or_neighbours(&g, p, nb);
-        for (int j = 0; j < k; ++j) D[p * N + nb[j]] = or_weight(&g, p, nb[j]);
+        int64_t k = or_neighbours(&g, p, nb, wb);
+        for (int64_t j = 0; j < k; ++j) D[p * N + nb[j]] = wb[j];
     }
     for (int64_t k = 0; k < N; ++k)
         for (int64_t i = 0; i < N; ++i) {
@@ -223,11 +261,8 @@ int gapd_oracle_floyd(const uint8_t *img, int H, int W, int C, int conn, int wmo
 
 /* Rows of the distances array for K given sources (one propagation each);
  * out receives K*N int32.  The naive method (Section 1) is sources = 0..N-1. */
-int gapd_oracle_rows(const uint8_t *img, int H, int W, int C, int conn, int wmode,
-                     const int32_t *sources, int64_t K, int32_t *out, int nthreads) {
-    or_graph g;
-    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
-    if (st) return st;
+static int or_rows(const or_graph *gp, const int32_t *sources, int64_t K, int32_t *out, int nthreads) {
+    const or_graph g = *gp;
     if (!out || K < 0 || (K > 0 && !sources)) return OR_EINVAL;
     for (int64_t k = 0; k < K; ++k)
         if (sources[k] < 0 || sources[k] >= g.N) return OR_EINVAL;
@@ -252,6 +287,14 @@ int gapd_oracle_rows(const uint8_t *img, int H, int W, int C, int conn, int wmod
     return err;
 }
 
+int gapd_oracle_rows(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                     const int32_t *sources, int64_t K, int32_t *out, int nthreads) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    return or_rows(&g, sources, K, out, nthreads);
+}
+
 /* The naive method (Section 1): N propagations, one per pixel; D is N*N int32. */
 int gapd_oracle_naive(const uint8_t *img, int H, int W, int C, int conn, int wmode,
                       int32_t *D, int nthreads) {
@@ -269,23 +312,29 @@ int gapd_oracle_naive(const uint8_t *img, int H, int W, int C, int conn, int wmo
 /* Geodesic tree of a propagation (Section 2: root, nodes, leaves): parent of
  * v is the smallest-index neighbour q with dist(q) + w(q,v) == dist(v); the
  * root (dist 0, a seed) gets parent -1.  Computed from the final distances. */
+static int or_parents(const or_graph *g, const int64_t *dist, int32_t *parent) {
+    int64_t *nb = (int64_t *)malloc((size_t)(2 * g->maxdeg + 2) * sizeof(int64_t)), *wb = nb + g->maxdeg + 1;
+    if (!nb) return OR_ENOMEM;
+    for (int64_t v = 0; v < g->N; ++v) {
+        parent[v] = -1;
+        if (dist[v] == 0) continue;
+        int64_t k = or_neighbours(g, v, nb, wb);
+        for (int64_t j = 0; j < k; ++j)  /* the weights are symmetric: w(q,v) = w(v,q) */
+            if (dist[nb[j]] + wb[j] == dist[v]) {
+                const int better = ORACLE_MUTANT == 1 ? nb[j] > parent[v] : (parent[v] < 0 || nb[j] < parent[v]);
+                if (better) parent[v] = (int32_t)nb[j];
+            }
+    }
+    free(nb);
+    return OR_OK;
+}
+
 int gapd_oracle_parents(const uint8_t *img, int H, int W, int C, int conn, int wmode,
                         const int64_t *dist, int32_t *parent) {
     or_graph g;
     int st = or_graph_init(&g, img, H, W, C, conn, wmode);
     if (st) return st;
-    int64_t nb[8];
-    for (int64_t v = 0; v < g.N; ++v) {
-        parent[v] = -1;
-        if (dist[v] == 0) continue;
-        int k = or_neighbours(&g, v, nb);
-        for (int j = 0; j < k; ++j)
-            if (dist[nb[j]] + or_weight(&g, nb[j], v) == dist[v]) {
-                parent[v] = (int32_t)nb[j];
-                if (ORACLE_MUTANT != 1) break;
-            }
-    }
-    return OR_OK;
+    return or_parents(&g, dist, parent);
 }
 
 /* Geodesic centroid and decreasing list of geodesic extrema (Section 3.3):
@@ -300,19 +349,15 @@ static int or_cmp_rank(const void *a, const void *b) {
     return i < j ? -1 : (i > j ? 1 : 0);
 }
 
-int gapd_oracle_extrema(const uint8_t *img, int H, int W, int C, int conn, int wmode,
-                        int32_t *centroid, int64_t *d_edge, int64_t *d_c, int32_t *rank) {
-    or_graph g;
-    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
-    if (st) return st;
+static int or_extrema(const or_graph *gp, int32_t *centroid, int64_t *d_edge, int64_t *d_c, int32_t *rank) {
+    const or_graph g = *gp;
+    int st;
     int64_t nb = 0;
     int64_t *seeds = (int64_t *)malloc((size_t)g.N * sizeof(int64_t));
     int64_t *order = (int64_t *)malloc((size_t)g.N * sizeof(int64_t));
     if (!seeds || !order) { free(seeds); free(order); return OR_ENOMEM; }
-    for (int64_t p = 0; p < g.N; ++p) {
-        int y = (int)(p / W), x = (int)(p % W);
-        if (y == 0 || (y == H - 1 && ORACLE_MUTANT != 7) || x == 0 || x == W - 1) seeds[nb++] = p;
-    }
+    for (int64_t p = 0; p < g.N; ++p)
+        if (or_is_boundary(&g, p)) seeds[nb++] = p;
     st = or_dijkstra(&g, seeds, nb, d_edge);
     if (!st) {
         int64_t c = 0;
@@ -329,6 +374,14 @@ int gapd_oracle_extrema(const uint8_t *img, int H, int W, int C, int conn, int w
     }
     free(seeds); free(order);
     return st;
+}
+
+int gapd_oracle_extrema(const uint8_t *img, int H, int W, int C, int conn, int wmode,
+                        int32_t *centroid, int64_t *d_edge, int64_t *d_c, int32_t *rank) {
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    return or_extrema(&g, centroid, d_edge, d_c, rank);
 }
 
 /* ---- spiral turns (Section 3.1) ------------------------------------------------------- */
@@ -389,13 +442,14 @@ typedef struct {
  *              picks the floor(r * |S| / 2^32)-th member of S in turn order
  *   n_rnd      length of rnd; the call fails with OR_EINVAL if it runs out
  * Returns OR_TRUNCATED when max_steps (>= 0) stops the loop early. */
-static int or_tree_methods(const uint8_t *img, int H, int W, int C, int conn, int wmode, int rule, int h,
-                           const uint32_t *rnd, int64_t n_rnd, int32_t *D, int32_t *seq_out, int64_t *a_out,
-                           int64_t *n_prop, int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
-    or_graph g;
-    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
-    if (st) return st;
+static int or_tree_methods(const or_graph *gp, int rule, int h, const uint32_t *rnd, int64_t n_rnd, int32_t *D,
+                           int32_t *seq_out, int64_t *a_out, int64_t *n_prop, int32_t *centroid_out,
+                           int32_t *rank_out, int64_t max_steps) {
+    const or_graph g = *gp;
+    const int H = g.H, W = g.W;
+    int st = OR_OK;
     if (!D || !n_prop) return OR_EINVAL;
+    if (rule == OR_RULE_SPIRAL && g.rp) return OR_EINVAL; /* spiral turns need a pixel grid */
     if (rule == OR_RULE_SPIRAL && !rnd && n_rnd > 0) return OR_EINVAL;
     const int64_t N = g.N;
     uint8_t *mrk = (uint8_t *)calloc((size_t)(N * N), 1);
@@ -411,7 +465,7 @@ static int or_tree_methods(const uint8_t *img, int H, int W, int C, int conn, in
     /* The geodesic centroid and the decreasing list of geodesic extrema
      * (Section 3.3); dc keeps the distances from the centroid. */
     int32_t c;
-    st = gapd_oracle_extrema(img, H, W, C, conn, wmode, &c, da, dc, rank);
+    st = or_extrema(&g, &c, da, dc, rank);
     if (st) goto done;
     if (centroid_out) *centroid_out = c;
     if (rank_out) memcpy(rank_out, rank, (size_t)N * sizeof(int32_t));
@@ -485,7 +539,8 @@ static int or_tree_methods(const uint8_t *img, int H, int W, int C, int conn, in
         /* Compute the geodesic tree from s. */
         st = or_dijkstra(&g, &s, 1, da);
         if (st) goto done;
-        gapd_oracle_parents(img, H, W, C, conn, wmode, da, parent);
+        st = or_parents(&g, da, parent);
+        if (st) goto done;
 
         /* Fill D along the tree (Property 1): each ancestor u of v gives
          * d(u,v) = d(s,v) - d(s,u). */
@@ -528,8 +583,11 @@ done:
 int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, int wmode,
                              int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
                              int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
-    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_FILLING, 0, NULL, 0, D, seq_out, a_out, n_prop,
-                           centroid_out, rank_out, max_steps);
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    return or_tree_methods(&g, OR_RULE_FILLING, 0, NULL, 0, D, seq_out, a_out, n_prop, centroid_out, rank_out,
+                           max_steps);
 }
 
 /* The geodesic extrema method (Section 3.3, algorithm "extrema"): the source
@@ -538,8 +596,11 @@ int gapd_oracle_filling_rate(const uint8_t *img, int H, int W, int C, int conn, 
 int gapd_oracle_extrema_method(const uint8_t *img, int H, int W, int C, int conn, int wmode,
                                int32_t *D, int32_t *seq_out, int64_t *a_out, int64_t *n_prop,
                                int32_t *centroid_out, int64_t max_steps) {
-    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_EXTREMA, 0, NULL, 0, D, seq_out, a_out, n_prop,
-                           centroid_out, NULL, max_steps);
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    return or_tree_methods(&g, OR_RULE_EXTREMA, 0, NULL, 0, D, seq_out, a_out, n_prop, centroid_out, NULL,
+                           max_steps);
 }
 
 /* The spiral method (Section 3.1, algorithm "spiral"; h <= 1) and the spiral
@@ -549,6 +610,143 @@ int gapd_oracle_extrema_method(const uint8_t *img, int H, int W, int C, int conn
 int gapd_oracle_spiral(const uint8_t *img, int H, int W, int C, int conn, int wmode, int h,
                        const uint32_t *rnd, int64_t n_rnd, int32_t *D, int32_t *seq_out, int64_t *a_out,
                        int64_t *n_prop, int64_t max_steps) {
-    return or_tree_methods(img, H, W, C, conn, wmode, OR_RULE_SPIRAL, h, rnd, n_rnd, D, seq_out, a_out, n_prop,
-                           NULL, NULL, max_steps);
+    or_graph g;
+    int st = or_graph_init(&g, img, H, W, C, conn, wmode);
+    if (st) return st;
+    return or_tree_methods(&g, OR_RULE_SPIRAL, h, rnd, n_rnd, D, seq_out, a_out, n_prop, NULL, NULL, max_steps);
+}
+
+/* ---- general graphs (Section 5: any graph, once its boundary vertices are known) ------- */
+
+/* Boundary vertices by the example rule of Section 5: fewer neighbours than
+ * the graph's average degree.  When no vertex qualifies (a regular graph),
+ * every vertex is a boundary vertex.  out: n flags. */
+int gapd_oracle_graph_boundary(int64_t n, const int64_t *rp, uint8_t *out) {
+    if (n < 1 || !rp || !out) return OR_EINVAL;
+    int64_t any = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        /* deg(v) < m / n, in integers */
+        out[v] = ORACLE_MUTANT == 12 ? (rp[v + 1] - rp[v]) * n <= rp[n] : (rp[v + 1] - rp[v]) * n < rp[n];
+        any += out[v];
+    }
+    if (!any)
+        for (int64_t v = 0; v < n; ++v) out[v] = 1;
+    return OR_OK;
+}
+
+/* A CSR graph is accepted when: rp[0] = 0, rows are nondecreasing, every
+ * neighbour id is in range and not the vertex itself, no row repeats a
+ * neighbour, every weight is >= 1, every edge (u, v, w) has its reverse
+ * (v, u, w), and the graph is connected.  bnd (nullable) gives the boundary
+ * flags; without it the degree rule is used (*owned then holds the flags). */
+static int or_csr_init(or_graph *g, int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                       const uint8_t *bnd, uint8_t **owned) {
+    memset(g, 0, sizeof(*g));
+    *owned = NULL;
+    if (n < 1 || !rp || rp[0] != 0) return OR_EINVAL;
+    for (int64_t v = 0; v < n; ++v)
+        if (rp[v + 1] < rp[v]) return OR_EINVAL;
+    const int64_t m = rp[n];
+    if (m > 0 && (!ci || !cw)) return OR_EINVAL;
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t deg = rp[v + 1] - rp[v];
+        if (deg > maxdeg) maxdeg = deg;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int64_t u = ci[e];
+            if (u < 0 || u >= n || u == v || cw[e] < 1) return OR_EINVAL;
+            for (int64_t f = rp[v]; f < e; ++f)
+                if (ci[f] == u) return OR_EINVAL;
+            int found = 0;
+            for (int64_t f = rp[u]; f < rp[u + 1]; ++f)
+                if (ci[f] == v && cw[f] == cw[e]) { found = 1; break; }
+            if (!found) return OR_EINVAL;
+        }
+    }
+    /* connected: a breadth-first search from vertex 0 reaches every vertex */
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    if (!queue || !seen) { free(queue); free(seen); return OR_ENOMEM; }
+    int64_t head = 0, tail = 0;
+    queue[tail++] = 0;
+    seen[0] = 1;
+    while (head < tail) {
+        const int64_t v = queue[head++];
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (!seen[ci[e]]) { seen[ci[e]] = 1; queue[tail++] = ci[e]; }
+    }
+    free(queue);
+    free(seen);
+    if (tail != n) return OR_EINVAL;
+    g->rp = rp; g->ci = ci; g->cw = cw; g->N = n; g->maxdeg = maxdeg;
+    if (bnd) {
+        g->bnd = bnd;
+    } else {
+        uint8_t *b = (uint8_t *)malloc((size_t)n);
+        if (!b) return OR_ENOMEM;
+        gapd_oracle_graph_boundary(n, rp, b);
+        g->bnd = b;
+        *owned = b;
+    }
+    return OR_OK;
+}
+
+/* Multi-seed propagation on a CSR graph (Section 1, on the graph of Section 5). */
+int gapd_oracle_graph_dijkstra(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                               const int64_t *seeds, int64_t nseeds, int64_t *dist) {
+    or_graph g;
+    uint8_t *owned;
+    int st = or_csr_init(&g, n, rp, ci, cw, NULL, &owned);
+    if (!st) st = (!dist || nseeds < 1 || !seeds) ? OR_EINVAL : or_dijkstra(&g, seeds, nseeds, dist);
+    free(owned);
+    return st;
+}
+
+/* Canonical geodesic-tree parents on a CSR graph (smallest-index tight neighbour). */
+int gapd_oracle_graph_parents(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                              const int64_t *dist, int32_t *parent) {
+    or_graph g;
+    uint8_t *owned;
+    int st = or_csr_init(&g, n, rp, ci, cw, NULL, &owned);
+    if (!st) st = or_parents(&g, dist, parent);
+    free(owned);
+    return st;
+}
+
+/* Rows of D for K sources on a CSR graph; the naive method is sources 0..n-1. */
+int gapd_oracle_graph_rows(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                           const int32_t *sources, int64_t K, int32_t *out, int nthreads) {
+    or_graph g;
+    uint8_t *owned;
+    int st = or_csr_init(&g, n, rp, ci, cw, NULL, &owned);
+    if (!st) st = or_rows(&g, sources, K, out, nthreads);
+    free(owned);
+    return st;
+}
+
+/* Geodesic centre and extrema ranks of a CSR graph, the first propagation
+ * starting from the boundary vertices (Section 5). */
+int gapd_oracle_graph_extrema(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                              const uint8_t *bnd, int32_t *centroid, int64_t *d_edge, int64_t *d_c, int32_t *rank) {
+    or_graph g;
+    uint8_t *owned;
+    int st = or_csr_init(&g, n, rp, ci, cw, bnd, &owned);
+    if (!st) st = or_extrema(&g, centroid, d_edge, d_c, rank);
+    free(owned);
+    return st;
+}
+
+/* The filling-rate method (rule 0) or the geodesic extrema method (rule 1)
+ * on a CSR graph.  Outputs as for gapd_oracle_filling_rate. */
+int gapd_oracle_graph_tree_method(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *cw,
+                                  const uint8_t *bnd, int rule, int32_t *D, int32_t *seq_out, int64_t *a_out,
+                                  int64_t *n_prop, int32_t *centroid_out, int32_t *rank_out, int64_t max_steps) {
+    if (rule != OR_RULE_FILLING && rule != OR_RULE_EXTREMA) return OR_EINVAL;
+    or_graph g;
+    uint8_t *owned;
+    int st = or_csr_init(&g, n, rp, ci, cw, bnd, &owned);
+    if (!st)
+        st = or_tree_methods(&g, rule, 0, NULL, 0, D, seq_out, a_out, n_prop, centroid_out, rank_out, max_steps);
+    free(owned);
+    return st;
 }

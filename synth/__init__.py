@@ -30,6 +30,7 @@ __all__ = [
     "hairpin_image",
     "deltar_images",
     "spiral_draws",
+    "geometric_graph",
     "config1",
     "config2",
     "config3",
@@ -109,6 +110,45 @@ def deltar_images(seed: int = 7, side: int = 25) -> dict:
 def spiral_draws(seed: int, n: int) -> np.ndarray:
     """n uniform 32-bit draws for the spiral methods' random selections."""
     return np.random.default_rng(seed).integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+
+
+def geometric_graph(rng: np.random.Generator, n: int, k: int = 6, wmax: int = 100):
+    """A connected undirected graph in CSR form (row_ptr int64, col int32,
+    weight int32), rows sorted by neighbour id.
+
+    n points uniform in the unit square; every point is joined to its k
+    nearest points, and consecutive points in x order are joined as well (a
+    chain that makes the graph connected).  An edge's weight is
+    1 + floor(wmax * sqrt(n) * |p - q|), the same in both directions, so it is
+    at least 1 and about wmax for a typical neighbour spacing.
+    """
+    from scipy.spatial import cKDTree
+    pts = rng.uniform(0.0, 1.0, size=(n, 2))
+    edges = set()
+    if n > 1:
+        kk = min(k + 1, n)
+        _, nn = cKDTree(pts).query(pts, k=kk)
+        nn = np.asarray(nn).reshape(n, kk)
+        for u in range(n):
+            for v in nn[u, 1:]:
+                v = int(v)
+                if v != u:
+                    edges.add((min(u, v), max(u, v)))
+        order = np.argsort(pts[:, 0], kind="stable")
+        for a, b in zip(order[:-1], order[1:]):
+            a, b = int(a), int(b)
+            edges.add((min(a, b), max(a, b)))
+    e = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    w = 1 + np.floor(wmax * np.sqrt(n) * np.linalg.norm(pts[e[:, 0]] - pts[e[:, 1]], axis=1)).astype(np.int64)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    ww = np.concatenate([w, w])
+    o = np.lexsort((dst, src))
+    src, dst, ww = src[o], dst[o], ww[o]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, src + 1, 1)
+    rp = np.cumsum(rp)
+    return rp, dst.astype(np.int32), ww.astype(np.int32)
 
 
 def voronoi_image(rng: np.random.Generator, h: int, w: int, bands: int = 8, n_seeds: int = 50,

@@ -2,8 +2,8 @@
 
 Each mutant is the oracle built with one deliberate error planted at compile
 time (a dropped term, a reversed tie rule, a one-sided fill, ...).  The pins of
-``test_oracle.py`` and ``test_oracle_methods.py`` are run against it in a
-subprocess and must fail.
+``test_oracle.py``, ``test_oracle_methods.py`` and ``test_oracle_graph.py``
+are run against it in a subprocess and must fail.
 """
 import os
 import subprocess
@@ -25,6 +25,7 @@ MUTANTS = {
     9: "extrema method takes the most filled of the farthest points",
     10: "spiral turns drop their left column",
     11: "spiral repulsion removes the pixels on one side of s only",
+    12: "graph boundary rule counts degrees equal to the average",
 }
 
 
@@ -36,6 +37,7 @@ def test_pins_reject_mutant(tmp_path, k):
     env = dict(os.environ, GAPD_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_methods.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_methods.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_graph.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {k} ({MUTANTS[k]}) passed every pin"
