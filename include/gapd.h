@@ -168,6 +168,45 @@ void gapd_destroy(gapd_ctx *ctx);
 const char *gapd_strerror(int status);
 const char *gapd_last_error(gapd_ctx *ctx);
 
+/* ---- general graphs (Section 5) --------------------------------------------------------- */
+
+/* The paper's methods apply to any graph once its boundary vertices are
+ * known: they replace the image border in the first propagation that finds
+ * the geodesic centre (Section 5).  A graph context holds an undirected
+ * graph in CSR form on the device.
+ *   n         vertices, 1 <= n <= 32768 (one propagation's distances and
+ *             frontier live in LDS)
+ *   row_ptr   HOST, n+1 int64: row v lists col_idx[row_ptr[v] .. row_ptr[v+1])
+ *   col_idx   HOST, int32 neighbour ids
+ *   weight    HOST, int32 edge weights, >= 1
+ *   boundary  HOST, nullable, n flags; null takes the example rule of
+ *             Section 5: the vertices with fewer neighbours than the average
+ *             degree (every vertex when none has); an all-zero mask is
+ *             refused
+ * Every edge must appear in both rows with the same weight, with no self
+ * loop and no repeated neighbour, and the graph must be connected, else
+ * GAPD_EINVAL.  Every distance is at most the total weight of the
+ * breadth-first spanning tree from vertex 0; if that reaches 2^27 the call
+ * gives GAPD_ERANGE.  The arrays are copied.  gapd_last_error(NULL) explains a failed create. */
+typedef struct gapd_graph gapd_graph;
+int gapd_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const int32_t *weight,
+                      const uint8_t *boundary, gapd_graph **out);
+int gapd_graph_set_stream(gapd_graph *g, void *hip_stream);
+/* Workspace for GAPD_MODE_TREE_FILL_FR and _EXTREMA: the filled-pairs bit
+ * matrix, O(n) arrays and n 8-byte tree entries (0 for naive). */
+int gapd_graph_workspace_size(gapd_graph *g, int mode, size_t *bytes);
+int gapd_graph_set_workspace(gapd_graph *g, void *dev_ptr, size_t bytes);
+/* K propagations (Section 1): out[k*n + v] = d(sources[k], v); sources and
+ * out are DEVICE pointers; ids out of range give GAPD_EINVAL. */
+int gapd_graph_sssp(gapd_graph *g, const int32_t *sources, int K, int32_t *out);
+/* All of D (n x n int32, DEVICE) by GAPD_MODE_NAIVE, GAPD_MODE_TREE_FILL_FR
+ * or GAPD_MODE_TREE_FILL_EXTREMA (other modes: GAPD_EINVAL).  The geodesic
+ * tree of a propagation gives each vertex the smallest-index neighbour q
+ * with d(q) + w(q,v) = d(v) as parent; st as for gapd_all_pairs. */
+int gapd_graph_all_pairs(gapd_graph *g, int mode, int32_t *out, gapd_stats *st);
+const char *gapd_graph_last_error(gapd_graph *g);
+void gapd_graph_destroy(gapd_graph *g);
+
 /* ---- many images in one launch ------------------------------------------------------------ */
 
 /* Workspace bytes for gapd_all_pairs_batched with these image sizes (host

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgapd.so")
-SOURCES = ["kernels.hip", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "capi.cpp", "server.cpp", "graph.cpp"]
 ARCH = os.environ.get("GAPD_OFFLOAD_ARCH", "gfx950")
 
 

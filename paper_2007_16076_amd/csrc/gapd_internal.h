@@ -98,6 +98,7 @@ struct FrState {
     int32_t *slot_src;
     int32_t *spec_list;
     int32_t *dbuf;             // N: distances of the setup propagations
+    uint64_t *gtree;           // general graphs: N tree entries, distance << 32 | parent (-1 at the root)
     int32_t *D;                // N * N output
     FrCtl *ctl;
     int32_t *seq_out;          // nullable, N
@@ -114,6 +115,34 @@ constexpr int kSpecSlots = 128; // trees kept in the cache (at most 256, a power
 // Workspace layout of a single-image filling-rate run (spec: with the cache).
 size_t fr_workspace_bytes(int N, bool spec = false);
 FrState fr_workspace_layout(void *ws, int N, bool spec = false);
+
+// A general undirected graph on the device, in CSR form (Section 5).
+struct GGraph {
+    int n;
+    int _pad;
+    const int64_t *rp;   // n + 1 row pointers
+    const int32_t *ci;   // neighbour ids
+    const int32_t *cw;   // edge weights, >= 1, symmetric
+    const uint8_t *bnd;  // n boundary flags
+};
+
+// Vertices a graph may have: the distance array and two frontier bitmaps of
+// one propagation live in LDS.
+constexpr int kGraphMaxN = 32768;
+
+// Workspace of a tree-method run on a graph: the grid layout plus the
+// 64-bit tree entries.
+size_t graph_workspace_bytes(int n);
+FrState graph_workspace_layout(void *ws, int n);
+
+// Graph launchers: K propagations into K rows; setup (boundary propagation,
+// centre, propagation from it, ranks); one loop step (select + propagate +
+// tree, then the fill).
+hipError_t launch_graph_rows(const GGraph &g, const int32_t *src_list, int src_base, int K, int32_t *out,
+                             int max_rounds, FrCtl *ctl, hipStream_t st);
+hipError_t launch_graph_setup(const GGraph &g, const FrState &fs, int max_rounds, hipStream_t st);
+hipError_t launch_graph_step(const GGraph &g, const FrState &fs, int max_rounds, hipStream_t st,
+                             hipEvent_t mid = nullptr);
 
 // One image of a batch, as the batched kernels see it.
 struct BImg {

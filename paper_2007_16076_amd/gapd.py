@@ -26,7 +26,9 @@ EXPORTED = [
     "gapd_create", "gapd_set_stream", "gapd_workspace_size", "gapd_set_workspace", "gapd_sssp",
     "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
     "gapd_all_pairs_batched", "gapd_server_create", "gapd_serve_submit", "gapd_serve_poll", "gapd_serve_wait",
-    "gapd_serve_release", "gapd_server_destroy",
+    "gapd_serve_release", "gapd_server_destroy", "gapd_graph_create", "gapd_graph_set_stream",
+    "gapd_graph_workspace_size", "gapd_graph_set_workspace", "gapd_graph_sssp", "gapd_graph_all_pairs",
+    "gapd_graph_last_error", "gapd_graph_destroy",
 ]
 
 
@@ -89,6 +91,14 @@ def load_library(path: str = LIB_PATH):
         "gapd_serve_wait": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I),
         "gapd_serve_release": ([P, ctypes.c_uint64], I),
         "gapd_server_destroy": ([P], None),
+        "gapd_graph_create": ([ctypes.c_int64, P, P, P, P, ctypes.POINTER(P)], I),
+        "gapd_graph_set_stream": ([P, P], I),
+        "gapd_graph_workspace_size": ([P, I, ctypes.POINTER(SZ)], I),
+        "gapd_graph_set_workspace": ([P, P, SZ], I),
+        "gapd_graph_sssp": ([P, P, I, P], I),
+        "gapd_graph_all_pairs": ([P, I, P, ctypes.POINTER(Stats)], I),
+        "gapd_graph_last_error": ([P], ctypes.c_char_p),
+        "gapd_graph_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -345,3 +355,76 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Graph:
+    """A general undirected graph in CSR form on the device (gapd_graph_create).
+
+    row_ptr (n+1 int64), col_idx and weight (int32) describe both directions of
+    every edge; boundary (n flags) is optional (default: degree below the
+    average)."""
+
+    def __init__(self, row_ptr, col_idx, weight, boundary=None, stream=None):
+        lib = load_library()
+        self._rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self._ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self._cw = np.ascontiguousarray(weight, dtype=np.int32)
+        self._bnd = None if boundary is None else np.ascontiguousarray(boundary, dtype=np.uint8)
+        self.n = self._rp.size - 1
+        h = ctypes.c_void_p()
+        st = lib.gapd_graph_create(self.n, self._rp.ctypes.data, self._ci.ctypes.data, self._cw.ctypes.data,
+                                   None if self._bnd is None else self._bnd.ctypes.data, ctypes.byref(h))
+        if st != OK:
+            raise GapdError(st, f"{strerror(st)}: {lib.gapd_graph_last_error(None).decode()}")
+        self._h = h
+        self._ws = None
+        _gcheck(lib.gapd_graph_set_stream(self._h, _stream_ptr(stream)), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().gapd_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ensure_workspace(self, mode: int):
+        import torch
+        n = ctypes.c_size_t()
+        _gcheck(load_library().gapd_graph_workspace_size(self._h, mode, ctypes.byref(n)), self._h)
+        if n.value == 0:
+            return
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        _gcheck(load_library().gapd_graph_set_workspace(self._h, _dptr(self._ws), self._ws.numel()), self._h)
+
+    def sssp(self, sources, out=None):
+        import torch
+        src = sources if isinstance(sources, torch.Tensor) else torch.as_tensor(np.asarray(sources, np.int32))
+        src = src.to(device="cuda", dtype=torch.int32).contiguous()
+        K = src.numel()
+        if out is None:
+            out = torch.empty((K, self.n), dtype=torch.int32, device="cuda")
+        _gcheck(load_library().gapd_graph_sssp(self._h, _dptr(src), K, _dptr(out)), self._h)
+        return out
+
+    def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None,
+                  time_kernels: bool = False):
+        import torch
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.int32, device="cuda")
+        self._ensure_workspace(mode)
+        st = Stats()
+        st.sources_out = _dptr(sources_out) if sources_out is not None else None
+        st.filled_out = _dptr(filled_out) if filled_out is not None else None
+        st.time_kernels = 1 if time_kernels else 0
+        _gcheck(load_library().gapd_graph_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
+        return out, _stats(st)
+
+
+def _gcheck(status: int, h):
+    if status not in (OK, PENDING):
+        raise GapdError(status, f"{strerror(status)}: {load_library().gapd_graph_last_error(h).decode()}")
