@@ -21,6 +21,9 @@ available):
              "random", "bumps" and "hairpin bend" (spiral methods averaged
              over --draw-seeds draw sequences), with filling-rate curves;
              then every tree method timed once on the 128x128 blob image
+  graph      a random geometric graph (CSR, 4096 vertices, 6 nearest
+             neighbours + an x-ordered chain, Euclidean integer weights):
+             filling-rate vs naive through the general-graph path (Section 5)
 
 Prints ONE JSON line.  Inputs are resident on the GPU when the timed region
 starts; the timed region is bracketed by torch.cuda.synchronize().
@@ -430,6 +433,51 @@ def deltar_line(args):
             "images": out, "blob128_all_methods": big}
 
 
+def graph_line(args):
+    """The general-graph path on a random geometric graph: filling rate vs naive."""
+    import torch
+    import synth
+    from paper_2007_16076_amd import gapd
+    n = 4096
+    rp, ci, cw = synth.geometric_graph(np.random.default_rng(11), n)
+    g = gapd.Graph(rp, ci, cw)
+    res = {}
+    for mode in (gapd.MODE_TREE_FILL_FR, gapd.MODE_NAIVE):
+        out = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        sts, ms = [], []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = g.all_pairs(mode, out=out, time_kernels=(mode != gapd.MODE_NAIVE))
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                ms.append((time.perf_counter() - t0) * 1e3)
+                sts.append(st)
+        res[mode] = (sts, ms)
+        log(f"[graph] mode={mode}: {np.mean(ms):.1f} ms, n_prop {sts[-1].n_prop}")
+    fst, fms = res[gapd.MODE_TREE_FILL_FR]
+    nst, nms = res[gapd.MODE_NAIVE]
+    s0 = fst[-1]
+    kern = float(np.mean([s.ms_kernel for s in nst]))
+    roof = roofline_hbm(4.0 * n * n, kern)
+    roof.update(kernel="k_graph_rows (one frontier Bellman-Ford propagation per workgroup, writes its row)",
+                algorithmic_bytes_per_launch=4 * n * n, avg_launch_ms=round(kern, 4), traffic=None)
+    return {"metric": METRIC, "value": n * n / (np.mean(fms) * 1e-3), "unit": "distance entries/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(fms)), 3),
+            "p50_ms": round(pct(fms, 50), 3), "p99_ms": round(pct(fms, 99), 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "graph", "n": n, "edges_directed": int(rp[-1]),
+                       "graph": "synth.geometric_graph(default_rng(11), 4096)", "mode": "tree_fill_filling_rate"},
+            "n_prop": int(s0.n_prop), "n_prop_setup": int(s0.n_prop_setup),
+            "propagation_saving_vs_naive": round(1.0 - (s0.n_prop + 2) / n, 4),
+            "fr_loop_kernel_ms": {"select_propagate": round(s0.ms_step_kernels, 3),
+                                  "fill": round(s0.ms_fill_kernels, 3)},
+            "rounds_per_propagation": round(s0.rounds / max(s0.n_prop + 2, 1), 1),
+            "naive": {"value": n * n / (np.mean(nms) * 1e-3), "ms_per_call": round(float(np.mean(nms)), 3),
+                      "kernel_ms": round(kern, 3)},
+            "roofline_naive": roof}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,7 +485,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="blob128",
                     choices=["blob128", "uniform32", "voronoi192", "batched", "serve", "hbmcopy", "blob128c8",
-                             "deltar"])
+                             "deltar", "graph"])
     ap.add_argument("--draw-seeds", type=int, default=10, help="deltar: draw sequences per spiral method")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -484,6 +532,8 @@ def main():
             line["cpu_baseline"] = cpu_baseline_fr(img, 8, line["n_prop"], args.cpu_seconds)
     elif args.workload == "deltar":
         line = deltar_line(args)
+    elif args.workload == "graph":
+        line = graph_line(args)
     elif args.workload == "batched":
         line = batched_line(args)
     elif args.workload == "hbmcopy":

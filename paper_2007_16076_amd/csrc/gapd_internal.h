@@ -90,12 +90,13 @@ struct FrState {
     uint32_t *packed;          // N: tree words (distance, complete-row flag, parent direction)
     uint32_t *full;            // ceil(N/32) words: bit i set once count[i] == N
     // Tree cache for speculative propagations (null when not used): kSpecSlots
-    // trees of N words, the slot of each source (-1: none), the source of each
-    // slot (-1: empty) and the current step's plan: kSpecK candidates, then
-    // the kSpecK slots they replace.
+    // slots of N words, the slot of each source (-1: none), the source and
+    // state of each slot, and the current step's plan: kSpecK sources (-1:
+    // continue the slot's propagation), then the kSpecK slots.
     uint32_t *cache;
     int32_t *src_slot;
     int32_t *slot_src;
+    int32_t *slot_state;       // free, ready (tree words) or running (a partial distance field)
     int32_t *spec_list;
     int32_t *dbuf;             // N: distances of the setup propagations
     uint64_t *gtree;           // general graphs: N tree entries, distance << 32 | parent (-1 at the root)

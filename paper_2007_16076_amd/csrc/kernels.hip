@@ -33,6 +33,12 @@ constexpr int kBig = 0x7FFFFFFF;
 // filled-pairs matrix was already complete before this step, bits 5-31 the
 // distance from the source (< 2^27).
 constexpr uint32_t kFilledBit = 16u;
+
+// Slot states of the tree cache.
+constexpr int kSlotFree = 0;     // no tree
+constexpr int kSlotReady = 1;    // holds the tree words of slot_src
+constexpr int kSlotRunning = 2;  // holds the partial distance field of slot_src's propagation
+
 __host__ __device__ inline uint32_t tree_word(int d, uint32_t code) { return ((uint32_t)d << 5) | code; }
 __host__ __device__ inline int tw_dist(uint32_t w) { return (int)(w >> 5); }
 __host__ __device__ inline uint32_t tw_code(uint32_t w) { return w & 15u; }
@@ -538,7 +544,10 @@ __device__ void fr_init_range(const FrState &fs, int i0, int stride) {
     if (fs.src_slot)
         for (int i = i0; i < (fs.N > kSpecSlots ? fs.N : kSpecSlots); i += stride) {
             if (i < fs.N) fs.src_slot[i] = -1;
-            if (i < kSpecSlots) fs.slot_src[i] = -1;
+            if (i < kSpecSlots) {
+                fs.slot_src[i] = -1;
+                fs.slot_state[i] = kSlotFree;
+            }
         }
     for (int i = i0; i < fs.N; i += stride) {
         fs.mask[(size_t)i * fs.MW + (i >> 5)] = 1u << (i & 31);
@@ -692,7 +701,7 @@ __device__ __forceinline__ uint64_t key_heur(uint64_t k) {
 // The source of the step by a deterministic rule, -1 when D is filled.
 template <int RULE>
 __device__ int fr_select(const FrState &fs, uint64_t *red) {
-    constexpr int U = 8;  // independent loads in flight per thread
+    constexpr int U = 16;  // independent loads in flight per thread
     const int32_t *aux = sel_aux<RULE>(fs);
     uint64_t best = kNoKey;
     const int step = blockDim.x * U;
@@ -839,39 +848,49 @@ __device__ int spiral_select(const FrState &fs, uint64_t *red) {
     return turn_pixel(tn, W, pos);
 }
 
-// Ascending bitonic sorts in LDS of a[0 .. 2 * blockDim.x) and, in the same
-// passes, of b[0 .. nb) (nb a power of two, at most 2 * blockDim.x; the
-// stages of the shorter sort are a prefix of those of the longer one).
-__device__ void block_bitonic_sort2(uint64_t *a, uint64_t *b, int nb) {
-    const int n = 2 * blockDim.x, t = threadIdx.x;
-    for (int size = 2; size <= n; size <<= 1)
+// Ascending bitonic sort of 128 keys held two per lane across one wave
+// (lane l holds elements 2l and 2l+1): 28 compare-exchange stages, the
+// stride-1 ones inside a lane, the others through lane shuffles.
+__device__ __forceinline__ void wave_sort128(uint64_t &a, uint64_t &b) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            const int i = (t / stride) * 2 * stride + (t % stride), jj = i + stride;
-            const bool up = (i & size) == 0;
-            const uint64_t x = a[i], y = a[jj];
-            if ((x > y) == up) { a[i] = y; a[jj] = x; }
-            if (size <= nb && jj < nb) {
-                const uint64_t u = b[i], v = b[jj];
-                if ((u > v) == up) { b[i] = v; b[jj] = u; }
+            const bool up = ((2 * lane) & size) == 0;
+            if (stride == 1) {
+                const bool sw = (a > b) == up;
+                const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+                a = lo;
+                b = hi;
+            } else {
+                const int m = stride >> 1;
+                const uint64_t pa = __shfl_xor(a, m), pb = __shfl_xor(b, m);
+                const bool keep_min = ((lane & m) == 0) == up;
+                a = keep_min ? (pa < a ? pa : a) : (pa > a ? pa : a);
+                b = keep_min ? (pb < b ? pb : b) : (pb > b ? pb : b);
             }
         }
-    __syncthreads();
+    }
 }
 
-// fr_select, and from the same pass the speculation plan for this step.
-// Candidates: the points with the smallest keys other than the selected one,
-// among those whose rows are incomplete and whose trees are not cached (each
-// thread keeps its two best, the block sorts them).  Victims: the cache
-// slots in eviction order, free slots first, then slots whose source's row
-// is complete, then by decreasing key of their source; the slot holding the
-// selected point's tree is never a victim.  Candidate j replaces victim j
-// while its key is the smaller one.  The plan goes to fs.spec_list
-// (candidates, then victim slots), its length to *n_plan.
+// fr_select, and from the same pass the speculation plan for this step: a
+// list of at most kSpecK propagation pieces for the fill launch.  First every
+// running propagation continues (those whose source's row became complete
+// are dropped).  Then new candidates start: the points with the smallest keys
+// other than the selected one, among those whose rows are incomplete and
+// that have no slot (each thread keeps its two best; each wave sorts its
+// 128, the block merges the four best 32s).  Each new candidate takes a
+// victim slot, in eviction order: free slots, then ready slots whose
+// source's row is complete, then ready slots by decreasing key of their
+// source; running slots and the selected point's slot are never victims.
+// Candidate j replaces victim j while its key is the smaller one.  The list
+// goes to fs.spec_list (source, or -1 to continue; then the slot), its
+// length to *n_plan.
 template <int RULE>
 __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, uint64_t *skeys, int *n_plan) {
-    constexpr int U = 8;
-    constexpr uint64_t kTop = (1ull << 46) - 1;
+    constexpr int U = 32;  // three loads each: the whole pass is a few round trips
+    constexpr uint64_t kTop = (1ull << 46) - 1, kPinned = (1ull << 50) - 1;
     const int32_t *aux = sel_aux<RULE>(fs);
     uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
     const int step = blockDim.x * U;
@@ -900,34 +919,81 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
     const int s = key_done<RULE>(fs, best) ? -1 : key_point<RULE>(fs, best);
     if (c1 == best) { c1 = c2; c2 = kNoKey; }
     else if (c2 == best) c2 = kNoKey;
-    keys[2 * threadIdx.x] = c1;
-    keys[2 * threadIdx.x + 1] = c2;
-    // eviction order: (keep value << 8) | slot, keep value 0 for a free slot,
-    // 1 for a complete row, 2 + (kTop - coarse key) otherwise, all ones when pinned
-    if (threadIdx.x < kSpecSlots) {
-        const int src = fs.slot_src[threadIdx.x];
+    // slots (kSpecSlots = 128, the first two waves): running ones continue,
+    // the others get an eviction key
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    __shared__ int n_run;
+    if (threadIdx.x == 0) n_run = 0;
+    __syncthreads();
+    uint64_t e0 = ~0ull, e1 = ~0ull;
+    if (wave < kSpecSlots / 64) {
+        const int t = threadIdx.x;
+        const int src = fs.slot_src[t];
+        const int st = fs.slot_state[t];
+        const int cs = src >= 0 ? fs.count[src] : 0;
         uint64_t keep;
-        if (src < 0) keep = 0;
-        else if (src == s) keep = (1ull << 50) - 1;
-        else {
-            const int cs = fs.count[src];
+        if (st == kSlotRunning && cs < fs.N) {
+            keep = kPinned;
+            const int j = atomicAdd(&n_run, 1);
+            if (j < kSpecK) {
+                fs.spec_list[j] = -1;
+                fs.spec_list[kSpecK + j] = t;
+            }
+        } else if (src < 0 || st == kSlotFree || (st == kSlotRunning && cs >= fs.N)) {
+            keep = 0;  // free, or a propagation no longer needed
+        } else if (src == s) {
+            keep = kPinned;
+        } else {
             keep = cs >= fs.N ? 1 : 2 + (kTop - key_heur<RULE>(sel_key<RULE>(fs, src, cs, aux[src])));
         }
-        skeys[threadIdx.x] = (keep << 8) | (uint64_t)threadIdx.x;
+        // two slot keys per lane: slot t goes to element t of the wave pair
+        skeys[t] = (keep << 8) | (uint64_t)t;
     }
-    block_bitonic_sort2(keys, skeys, kSpecSlots);
+    __syncthreads();
+    // candidates: each wave sorts its 128, keeps its best 32
+    wave_sort128(c1, c2);
+    if (lane < 16) {
+        keys[wave * 32 + 2 * lane] = c1;
+        keys[wave * 32 + 2 * lane + 1] = c2;
+    }
+    if (wave == 2) {  // the slot keys, two per lane
+        e0 = skeys[2 * lane];
+        e1 = skeys[2 * lane + 1];
+        wave_sort128(e0, e1);
+    }
+    __syncthreads();
+    if (wave == 2) {
+        skeys[2 * lane] = e0;
+        skeys[2 * lane + 1] = e1;
+    }
+    if (wave == 0) {
+        uint64_t m0 = keys[2 * lane], m1 = keys[2 * lane + 1];
+        wave_sort128(m0, m1);
+        if (lane < 16) {
+            keys[128 + 2 * lane] = m0;
+            keys[128 + 2 * lane + 1] = m1;
+        }
+    }
+    __syncthreads();
+    const int nr = n_run < kSpecK ? n_run : kSpecK;
     if (threadIdx.x < kSpecK) {
-        const uint64_t ck = keys[threadIdx.x];
-        const uint64_t keep = skeys[threadIdx.x] >> 8;
-        const bool take = ck != kNoKey && (keep < 2 || key_heur<RULE>(ck) < kTop - (keep - 2));
-        fs.spec_list[threadIdx.x] = ck == kNoKey ? -1 : key_point<RULE>(fs, ck);
-        fs.spec_list[kSpecK + threadIdx.x] = (int)(skeys[threadIdx.x] & 0xFFu);
-        keys[kSpecK + threadIdx.x] = take ? 1 : 0;  // 'take' is monotone in j: a prefix
+        const int j = threadIdx.x;
+        bool take = false;
+        if (j >= nr) {
+            const uint64_t ck = keys[128 + (j - nr)];
+            const uint64_t keep = skeys[j - nr] >> 8;
+            take = ck != kNoKey && keep != kPinned && (keep < 2 || key_heur<RULE>(ck) < kTop - (keep - 2));
+            if (take) {
+                fs.spec_list[j] = key_point<RULE>(fs, ck);
+                fs.spec_list[kSpecK + j] = (int)(skeys[j - nr] & 0xFFu);
+            }
+        }
+        keys[256 + j] = (j < nr || take) ? 1 : 0;  // 'take' is monotone in j: a prefix
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int n = 0;
-        while (n < kSpecK && keys[kSpecK + n]) ++n;
+        while (n < kSpecK && keys[256 + n]) ++n;
         *n_plan = n;
     }
     return s;
@@ -959,7 +1025,8 @@ __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_
         }
         return;
     }
-    const int slot = kSpec ? fs.src_slot[s] : -1;
+    int slot = kSpec ? fs.src_slot[s] : -1;
+    if (slot >= 0 && fs.slot_state[slot] != kSlotReady) slot = -1;  // still propagating: compute it here
     if (threadIdx.x == 0) {
         if (fs.seq_out) fs.seq_out[ctl->n_prop] = s;
         ctl->s = s;
@@ -1164,18 +1231,20 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
 }
 
-// Propagation of speculative candidate j into its victim slot of the tree
-// cache (never the slot this step's fill reads).  One block.
+// Piece j of the speculation plan, one round of a propagation into its
+// cache slot: a new candidate starts in its victim slot (source at 0, the
+// rest infinite), a running one resumes from the partial distance field kept
+// in its slot.  A round that changes nothing ends the propagation (the field
+// is the fixed point): the tree words replace the field and the slot is
+// ready.  Otherwise the field goes back to the slot.  Any state of the field
+// is a set of real path lengths, so resuming converges to the same
+// distances.  One round stays shorter than the fill it runs beside, so the
+// speculation never lengthens a step.  One block.
 template <int CONN, int S, bool kStageW>
-__device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, int j) {
+__device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
     FrCtl *ctl = fs.ctl;
     if (j >= ctl->spec_n) return;
     const int c = fs.spec_list[j], sl = fs.spec_list[kSpecK + j];
-    if (threadIdx.x == 0) {
-        const int old = fs.slot_src[sl];
-        if (old >= 0) fs.src_slot[old] = -1;
-        fs.slot_src[sl] = -1;
-    }
     uint32_t *tree = fs.cache + (size_t)sl * fs.N;
     int *d = smem;
     NbW w = nbw_of(g);
@@ -1193,24 +1262,41 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int max_
             w.wdl = (const uint16_t *)(lw + 3 * half);
         }
     }
-    fill_inf(d, g.H * Wp);
-    __syncthreads();
-    if (threadIdx.x == 0) d[(c / g.W) * Wp + c % g.W] = 0;
+    if (c >= 0) {
+        if (threadIdx.x == 0) {
+            const int old = fs.slot_src[sl];
+            if (old >= 0) fs.src_slot[old] = -1;
+            fs.slot_src[sl] = c;
+            fs.src_slot[c] = sl;
+            fs.slot_state[sl] = kSlotRunning;
+        }
+        fill_inf(d, g.H * Wp);
+        __syncthreads();
+        if (threadIdx.x == 0) d[(c / g.W) * Wp + c % g.W] = 0;
+    } else {
+        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
+            const int y = v / g.W, x = v - y * g.W;
+            d[y * Wp + x] = (int)tree[v];
+        }
+    }
     __syncthreads();
     bool tree_done = false;
-    const int r = relax_block<CONN, S, false, true>(g, d, Wp, max_rounds, &w, tree, &tree_done);
-    if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, tree);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // A candidate that does not converge stays uncached: if it is ever
-        // selected, its own step reports the error.
-        if (r < 0) return;
-        fs.slot_src[sl] = c;
-        fs.src_slot[c] = sl;
-        atomicAdd((unsigned long long *)&ctl->spec_props, 1ull);
-        atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)r);
+    const int r = relax_block<CONN, S, false, true>(g, d, Wp, 1, &w, tree, &tree_done);
+    if (r >= 0) {
+        if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, tree);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            fs.slot_state[sl] = kSlotReady;
+            atomicAdd((unsigned long long *)&ctl->spec_props, 1ull);
+        }
+    } else {
+        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
+            const int y = v / g.W, x = v - y * g.W;
+            tree[v] = (uint32_t)d[y * Wp + x];
+        }
     }
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
 }
 
 // The fill of the current step (blocks kSpecK..) beside the speculative
@@ -1222,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs
     __shared__ int64_t red[4];
     if (fs.ctl->done) return;
     if ((int)blockIdx.x < kSpecK) {
-        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, blockIdx.x);
+        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, smem, blockIdx.x);
         return;
     }
     const int slot = fs.ctl->tree_slot;
@@ -1811,7 +1897,8 @@ size_t fr_workspace_bytes(int N, bool spec) {
     const size_t MW = ((size_t)N + 31) / 32;
     size_t b = al256((size_t)N * MW * 4) + 7 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
     if (spec)
-        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + al256(kSpecSlots * 4) + al256(2 * kSpecK * 4);
+        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + 2 * al256(kSpecSlots * 4) +
+             al256(2 * kSpecK * 4);
     return b;
 }
 
@@ -1833,6 +1920,7 @@ FrState fr_workspace_layout(void *ws, int N, bool spec) {
         f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * N * 4);
         f.src_slot = (int32_t *)p; p += al256((size_t)N * 4);
         f.slot_src = (int32_t *)p; p += al256(kSpecSlots * 4);
+        f.slot_state = (int32_t *)p; p += al256(kSpecSlots * 4);
         f.spec_list = (int32_t *)p;
     }
     return f;
