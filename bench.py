@@ -139,8 +139,8 @@ def run_single(args, name, img, conn, modes):
 
 def roofline_hbm(bytes_per_launch, ms):
     ach = bytes_per_launch / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None}
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 7), "traffic": None}
 
 
 def kernels_sha256():
@@ -215,15 +215,23 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
                      + (", beside the speculative propagations)" if spec else ")"),
                      algorithmic_bytes_per_launch=round(fill_bytes), avg_launch_ms=round(fill_ms, 5),
                      traffic=measured_traffic(workload, fill_name + "<"))
-    # a step launch propagates only when its source's tree was not cached
-    step_ops = 2.0 * E_dir * rounds * (n_prop - hits) / max(n_prop, 1)
-    ach = step_ops / (step_ms * 1e-3) / 1e12
-    roof_step = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
-                 "frac": round(ach / VALU_PEAK_TOPS, 6),
-                 "traffic": measured_traffic(workload, "k_fr_step_spec<" if spec else "k_fr_step<"),
-                 "kernel": ("k_fr_step_spec" if spec else "k_fr_step")
-                 + " (least-filled select + one propagation + tree unless cached, one workgroup)",
-                 "algorithmic_ops_per_launch": round(step_ops), "avg_launch_ms": round(step_ms, 5)}
+    if spec:
+        # With the tree cache a step launch is the select pass (count, rank or
+        # distance, and cache slot: 12 bytes per point read) plus, on a miss,
+        # one propagation writing N tree words.
+        step_bytes = 12.0 * N + 4.0 * N * (n_prop - hits) / max(n_prop, 1)
+        roof_step = roofline_hbm(step_bytes, step_ms)
+        roof_step.update(kernel="k_fr_step_spec (least-filled select and speculation plan; one propagation + "
+                                "tree on a cache miss; one workgroup)",
+                         algorithmic_bytes_per_launch=round(step_bytes), avg_launch_ms=round(step_ms, 5),
+                         traffic=measured_traffic(workload, "k_fr_step_spec<"))
+    else:
+        step_ops = 2.0 * E_dir * rounds
+        ach = step_ops / (step_ms * 1e-3) / 1e12
+        roof_step = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
+                     "frac": round(ach / VALU_PEAK_TOPS, 6), "traffic": measured_traffic(workload, "k_fr_step<"),
+                     "kernel": "k_fr_step (least-filled select + one propagation + tree, one workgroup)",
+                     "algorithmic_ops_per_launch": round(step_ops), "avg_launch_ms": round(step_ms, 5)}
     dominant, other = (roof_step, roof_fill) if step_ms >= fill_ms else (roof_fill, roof_step)
     value = N * N / (np.mean(fr_ms) * 1e-3)
     line.update(value=value, unit="distance entries/s", ms_per_step=round(float(np.mean(fr_ms)), 3),
