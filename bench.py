@@ -126,14 +126,21 @@ def run_single(args, name, img, conn, modes):
         for i in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, st = ctx.all_pairs(mode, out=out, time_kernels=(mode == gapd.MODE_TREE_FILL_FR))
+            _, st = ctx.all_pairs(mode, out=out)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) * 1e3
             log(f"[{name}] mode={mode} call {i}: {dt:.1f} ms (events {st.ms_total:.1f} ms) n_prop={st.n_prop}")
             if i >= args.warmup:
                 stats.append(st)
                 wall.append(dt)
-        res[mode] = (stats, wall)
+        kstats = stats
+        if mode != gapd.MODE_NAIVE:
+            # one more call, outside the timed ones, with every loop launch
+            # bracketed by events: the per-kernel durations of the roofline
+            _, st = ctx.all_pairs(mode, out=out, time_kernels=True)
+            torch.cuda.synchronize()
+            kstats = [st]
+        res[mode] = (stats, wall, kstats)
     return ctx, res
 
 
@@ -173,7 +180,7 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
     E_dir = edges_directed(img.shape[0], img.shape[1], conn)
     modes = [gapd.MODE_TREE_FILL_FR, gapd.MODE_NAIVE] if fr else [gapd.MODE_NAIVE]
     ctx, res = run_single(args, workload, img, conn, modes)
-    nst, nwall = res[gapd.MODE_NAIVE]
+    nst, nwall, _ = res[gapd.MODE_NAIVE]
     naive_ms = [s.ms_total for s in nst]
     naive_kernel_ms = float(np.mean([s.ms_kernel for s in nst]))
     naive_rounds = float(np.mean([s.rounds for s in nst])) / N
@@ -194,12 +201,12 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
                     p50_ms=naive["p50_ms"], p99_ms=naive["p99_ms"], naive=naive, roofline=roof_naive)
         line["config"]["mode"] = "naive"
         return line, ctx
-    fst, fwall = res[gapd.MODE_TREE_FILL_FR]
+    fst, fwall, kst = res[gapd.MODE_TREE_FILL_FR]
     fr_ms = [s.ms_total for s in fst]
-    s0 = fst[-1]
+    s0 = kst[-1]
     n_prop = s0.n_prop
-    step_ms = float(np.mean([s.ms_step_kernels for s in fst])) / max(n_prop, 1)
-    fill_ms = float(np.mean([s.ms_fill_kernels for s in fst])) / max(n_prop, 1)
+    step_ms = float(s0.ms_step_kernels) / max(n_prop, 1)
+    fill_ms = float(s0.ms_fill_kernels) / max(n_prop, 1)
     hits, n_spec = int(s0.n_cache_hits), int(s0.n_prop_speculative)
     spec = hits > 0 or n_spec > 0
     # rounds per propagation, over every propagation computed (setup, main

@@ -458,6 +458,9 @@ __device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int ma
         ++rounds;
         if (!__syncthreads_or(ch)) break;
         if (rounds >= max_rounds) return -1;
+        // A first round that changed anything is almost never the fixed point
+        // (paths with turns need a second one): sweep again before checking.
+        if (rounds == 1) continue;
         const NbW w = nw ? *nw : nbw_of(g);
         if (!__syncthreads_or(field_check<CONN, G, TREE>(g, w, d, Wp, tree))) {
             if (TREE) *tree_done = true;

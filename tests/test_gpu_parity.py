@@ -150,6 +150,32 @@ def test_filling_rate_blob_128_sampled(G, torch_mod, oracle_lib):
         assert seq[: st.n_prop].cpu().numpy().tolist() == g["sequence"]
 
 
+def test_filling_rate_voronoi_192_sampled(G, torch_mod, oracle_lib):
+    """Config-3 size (192x192x8 Voronoi, w = 1 + L1, N = 36864, D = 5.4 GB):
+    the filling-rate D equals the naive D everywhere (tree words fit LDS, the
+    counts do not: the other fill variant with the tree cache), sampled rows
+    equal the oracle's propagations, and a(t) ends at N(N-1)/2."""
+    import synth
+    img = synth.config3()
+    say("fr voronoi192")
+    ctx = G.Context(img)
+    torch = torch_mod
+    N = ctx.N
+    fil = torch.zeros((N,), dtype=torch.int64, device="cuda")
+    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, filled_out=fil)
+    torch.cuda.synchronize()
+    say("fr voronoi192 done", st.n_prop, st.ms_total, st.n_cache_hits)
+    assert int(fil[st.n_prop - 1]) == N * (N - 1) // 2
+    assert st.n_cache_hits > 0
+    rows = np.random.default_rng(8).choice(N, size=8, replace=False)
+    ref = oracle_lib.rows(img, rows)
+    assert np.array_equal(D[torch.as_tensor(rows, device="cuda")].cpu().numpy(), ref)
+    Dn, _ = ctx.all_pairs(G.MODE_NAIVE)
+    assert torch.equal(D, Dn)
+    del D, Dn
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------------------------- sssp
 
 def test_sssp_matches_oracle(G, torch_mod, oracle_lib):
