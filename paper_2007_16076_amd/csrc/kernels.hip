@@ -39,6 +39,12 @@ constexpr int kSlotFree = 0;     // no tree
 constexpr int kSlotReady = 1;    // holds the tree words of slot_src
 constexpr int kSlotRunning = 2;  // holds the partial distance field of slot_src's propagation
 
+// floor(v / W) by a multiply: with m = floor(2^32 / W) + 1, (v * m) >> 32 is
+// exact for v < 2^18 and W <= 512 (the product exceeds v / W by less than
+// v / 2^32 < 1 / W).
+__device__ __forceinline__ uint64_t divw_magic(int W) { return (1ull << 32) / (uint64_t)W + 1ull; }
+__device__ __forceinline__ int divw(int v, uint64_t m) { return (int)(((uint64_t)(uint32_t)v * m) >> 32); }
+
 __host__ __device__ inline uint32_t tree_word(int d, uint32_t code) { return ((uint32_t)d << 5) | code; }
 __host__ __device__ inline int tw_dist(uint32_t w) { return (int)(w >> 5); }
 __host__ __device__ inline uint32_t tw_code(uint32_t w) { return w & 15u; }
@@ -386,13 +392,14 @@ __device__ bool field_check(const GImg &g, const NbW &w, const int *d, int Wp, u
     constexpr int U = 8;
     bool bad = false;
     const int N = g.N, W = g.W;
+    const uint64_t mW = divw_magic(W);
     for (int base = threadIdx.x; base < N; base += blockDim.x * U) {
         int m[U], dv[U];
         uint32_t code[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int v = min(base + k * (int)blockDim.x, N - 1);
-            const int y = v / W, x = v - y * W;
+            const int y = divw(v, mW), x = v - y * W;
             int cand[8];
             neighbour_paths<CONN, G>(g, w, d, Wp, y, x, cand);
             dv[k] = ldd<G>(&d[y * Wp + x]);
@@ -530,8 +537,9 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
     }
     if (!kGlobal) {
+        const uint64_t mW = divw_magic(g.W);
         for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = v / g.W, x = v - y * g.W;
+            const int y = divw(v, mW), x = v - y * g.W;
             row[v] = d[y * Wp + x];
         }
     }
@@ -1277,8 +1285,9 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
         __syncthreads();
         if (threadIdx.x == 0) d[(c / g.W) * Wp + c % g.W] = 0;
     } else {
+        const uint64_t mW = divw_magic(g.W);
         for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = v / g.W, x = v - y * g.W;
+            const int y = divw(v, mW), x = v - y * g.W;
             d[y * Wp + x] = (int)tree[v];
         }
     }
@@ -1294,8 +1303,9 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
             atomicAdd((unsigned long long *)&ctl->spec_props, 1ull);
         }
     } else {
+        const uint64_t mW = divw_magic(g.W);
         for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = v / g.W, x = v - y * g.W;
+            const int y = divw(v, mW), x = v - y * g.W;
             tree[v] = (uint32_t)d[y * Wp + x];
         }
     }
@@ -1365,8 +1375,9 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
     }
     int32_t *row = out + bi.out_off + (size_t)s * g.N;
+    const uint64_t mW = divw_magic(g.W);
     for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-        const int y = v / g.W, x = v - y * g.W;
+        const int y = divw(v, mW), x = v - y * g.W;
         row[v] = d[y * Wp + x];
     }
 }
