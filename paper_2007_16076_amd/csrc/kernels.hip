@@ -1172,13 +1172,91 @@ __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, 
     return nnew;
 }
 
+// fill_from with a grandparent table a2 (0xFFFF: none) beside the tree words
+// in LDS: one round of LDS reads (the tree words of the parent and of the
+// grandparent, and the grandparent's own grandparent) advances the walk by
+// two ancestors, so the dependent chain of reads is half as long.
+template <int PF, bool kCntLds>
+__device__ int fill_from2(const FrState &fs, const uint32_t *pk, const uint16_t *a2, int W, int v, int s, int *cnt) {
+    constexpr int P2 = PF / 2;
+    const int N = fs.N, MW = fs.MW;
+    const uint32_t wv = pk[v];
+    const int dv = tw_dist(wv);
+    uint32_t *mrow = fs.mask + (size_t)v * MW;
+    int32_t *Drow = fs.D + (size_t)v * N;
+    int cur = v;
+    uint32_t tcur = wv;
+    int gcur = a2[v] == 0xFFFFu ? -1 : (int)a2[v];
+    // the next two ancestors a (parent of cur) and b (its parent, -1 past the root)
+    auto gen = [&](int &a, int &b, int &da, int &db, uint32_t &ba, uint32_t &bb) {
+        if (cur < 0) {
+            a = b = -1;
+            return;
+        }
+        const uint32_t code = tw_code(tcur);
+        a = code == kRootCode ? -1 : cur + code_dy((int)code) * W + code_dx((int)code);
+        b = a < 0 ? -1 : gcur;
+        const int ac = a < 0 ? v : a, bc = b < 0 ? v : b;  // in-range addresses
+        const uint32_t ta = pk[ac], tb = pk[bc];
+        const uint16_t gb = a2[bc];
+        da = tw_dist(ta);
+        db = tw_dist(tb);
+        ba = 0xFFFFFFFFu;
+        bb = 0xFFFFFFFFu;
+        if (!(ta & kFilledBit)) ba = mrow[ac >> 5];
+        if (!(tb & kFilledBit)) bb = mrow[bc >> 5];
+        cur = b;
+        tcur = tb;
+        gcur = gb == 0xFFFFu ? -1 : (int)gb;
+    };
+    int nnew = 0;
+    auto handle = [&](int u, int du, uint32_t bits) {
+        if ((bits >> (u & 31)) & 1u) return;
+        const int val = dv - du;
+        Drow[u] = val;
+        fs.D[(size_t)u * N + v] = val;
+        atomicOr(&mrow[u >> 5], 1u << (u & 31));
+        if (u != s) {
+            atomicOr(&fs.mask[(size_t)u * MW + (v >> 5)], 1u << (v & 31));
+            if (kCntLds)
+                atomicAdd(&cnt[u], 1);
+            else
+                count_add(fs, u, 1);
+        }
+        ++nnew;
+    };
+    int pa[P2], pb[P2], qa[P2], qb[P2];
+    uint32_t ra[P2], rb[P2];
+#pragma unroll
+    for (int k = 0; k < P2; ++k) gen(pa[k], pb[k], qa[k], qb[k], ra[k], rb[k]);
+    bool alive = true;
+    while (alive) {
+#pragma unroll
+        for (int k = 0; k < P2; ++k) {
+            if (alive) {
+                if (pa[k] < 0) {
+                    alive = false;
+                } else {
+                    handle(pa[k], qa[k], ra[k]);
+                    if (pb[k] < 0)
+                        alive = false;
+                    else
+                        handle(pb[k], qb[k], rb[k]);
+                }
+                if (alive) gen(pa[k], pb[k], qa[k], qb[k], ra[k], rb[k]);
+            }
+        }
+    }
+    return nnew;
+}
+
 // Fill D along the current tree (many blocks).  The tree words are staged in
 // LDS when they fit, and so are the count increments of the ancestors: the
 // few ancestors near the source collect thousands of increments per step,
 // which would serialise as same-address atomics in L2, so each block sums
 // them in LDS and adds its totals once.  The source's own row becomes
 // complete: block 0 marks it.
-template <bool kLds, bool kLdsCount>
+template <bool kLds, bool kLdsCount, bool kA2 = false>
 __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *spk, int64_t *red, int chunk,
                               int nchunks) {
     const FrCtl *ctl = fs.ctl;
@@ -1208,10 +1286,26 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
         for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;
     }
     __syncthreads();
+    // grandparents, after the flags (which leave the parent codes alone)
+    uint16_t *a2 = (uint16_t *)(spk + N);
+    if (kA2) {
+        for (int x = threadIdx.x; x < N; x += blockDim.x) {
+            const uint32_t c1 = tw_code(spk[x]);
+            uint16_t g = 0xFFFFu;
+            if (c1 != kRootCode) {
+                const int p = x + code_dy((int)c1) * W + code_dx((int)c1);
+                const uint32_t c2 = tw_code(spk[p]);
+                if (c2 != kRootCode) g = (uint16_t)(p + code_dy((int)c2) * W + code_dx((int)c2));
+            }
+            a2[x] = g;
+        }
+        __syncthreads();
+    }
     int64_t mine = 0;
     for (int v = chunk * blockDim.x + threadIdx.x; v < N; v += nchunks * blockDim.x) {
         if (v == s || (pk[v] & kFilledBit)) continue;
-        const int n = fill_from<16, kLdsCount>(fs, pk, W, W, v, s, cnt);
+        const int n = kA2 ? fill_from2<16, kLdsCount>(fs, pk, a2, W, v, s, cnt)
+                          : fill_from<16, kLdsCount>(fs, pk, W, W, v, s, cnt);
         if (n) count_add(fs, v, n);
         mine += n;
     }
@@ -1315,7 +1409,7 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
 // The fill of the current step (blocks kSpecK..) beside the speculative
 // propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
 // that the longer propagations start at once).
-template <int CONN, int S, bool kStageW, bool kLdsCount>
+template <int CONN, int S, bool kStageW, bool kLdsCount, bool kA2 = false>
 __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ int64_t red[4];
@@ -1326,8 +1420,8 @@ __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs
     }
     const int slot = fs.ctl->tree_slot;
     const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
-    fr_fill_block<true, kLdsCount>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
-                                   gridDim.x - kSpecK);
+    fr_fill_block<true, kLdsCount, kA2>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
+                                        gridDim.x - kSpecK);
 }
 
 // Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
@@ -1460,10 +1554,10 @@ struct FrSetup {
 
 template <int CONN, int S>
 struct FrStep {
-    template <bool kStageW, bool kLdsCount>
+    template <bool kStageW, bool kLdsCount, bool kA2 = false>
     static hipError_t launch_fill_spec(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
                                        size_t lds, int blocks) {
-        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount>;
+        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount, kA2>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(kSpecK + blocks), dim3(256), lds, st, g, Wp, fs, max_rounds);
@@ -1501,7 +1595,13 @@ struct FrStep {
         if (spec) {
             // the fill beside the speculative propagations
             const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
-            if (2 * pk <= kMaxLds) {
+            const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
+            if (a2 <= kMaxLds && g.N < 0xFFFF) {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks);
+                else
+                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks);
+            } else if (2 * pk <= kMaxLds) {
                 if (lds + wbytes <= kMaxLds)
                     e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
                 else
