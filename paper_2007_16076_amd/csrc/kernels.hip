@@ -324,21 +324,6 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
 __device__ __forceinline__ int code_dy(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
 __device__ __forceinline__ int code_dx(int k) { return k < 3 ? k - 1 : (k == 3 ? -1 : (k == 4 ? 1 : k - 6)); }
 
-// Weight of the edge between (y, x) and its neighbour in direction k.
-__device__ __forceinline__ int nb_weight(const GImg &g, int y, int x, int k) {
-    const int W = g.W;
-    switch (k) {
-        case 0: return g.wdr[(y - 1) * W + x - 1];
-        case 1: return g.wd[(y - 1) * W + x];
-        case 2: return g.wdl[(y - 1) * W + x + 1];
-        case 3: return g.wr[y * W + x - 1];
-        case 4: return g.wr[y * W + x];
-        case 5: return g.wdl[y * W + x];
-        case 6: return g.wd[y * W + x];
-        default: return g.wdr[y * W + x];
-    }
-}
-
 template <int CONN>
 __device__ __forceinline__ bool code_used(int k) {
     return CONN == 8 || k == 1 || k == 3 || k == 4 || k == 6;
