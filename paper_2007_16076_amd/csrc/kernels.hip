@@ -721,8 +721,9 @@ __device__ int fr_select(const FrState &fs, uint64_t *red) {
     return key_point<RULE>(fs, best);
 }
 
-// Block-wide exclusive prefix sum in thread order (red: one slot per wave).
-__device__ int block_excl_scan(int v, int64_t *red) {
+// Block-wide exclusive prefix sum in thread order (red: one slot per wave);
+// *total (optional) receives the block's sum.
+__device__ int block_excl_scan(int v, int64_t *red, int *total = nullptr) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     int x = v;
 #pragma unroll
@@ -733,9 +734,15 @@ __device__ int block_excl_scan(int v, int64_t *red) {
     __syncthreads();
     if (lane == 63) red[wave] = x;
     __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wave; ++w) base += (int)red[w];
+    int base = 0, all = 0;
+    const int nw = (int)(blockDim.x >> 6);
+    for (int w = 0; w < nw; ++w) {
+        const int r = (int)red[w];
+        base += w < wave ? r : 0;
+        all += r;
+    }
     __syncthreads();
+    if (total) *total = all;
     return base + x - v;
 }
 
@@ -1749,9 +1756,9 @@ __device__ int graph_relax_block(const GGraph &g, int *d, GFront f, int max_roun
         for (;;) {
             int c = 0;
             for (int w = threadIdx.x; w < nw; w += blockDim.x) c += __popc(f.cur[w]);
-            const int total = (int)block_sum_i64(c, red);
+            int total;
+            int pos = block_excl_scan(c, red, &total);
             if (total == 0) break;
-            int pos = block_excl_scan(c, red);
             for (int w = threadIdx.x; w < nw && pos < f.cap; w += blockDim.x) {
                 uint32_t b = f.cur[w];
                 while (b && pos < f.cap) {
@@ -1767,6 +1774,7 @@ __device__ int graph_relax_block(const GGraph &g, int *d, GFront f, int max_roun
                 graph_relax_edges(g, d, f.nxt, d[v], g.rp[v], g.rp[v + 1], any);
             }
             __syncthreads();
+            if (total <= f.cap) break;  // the whole frontier was listed
         }
         if (!__syncthreads_or(any)) return r;
         uint32_t *t = f.cur;
