@@ -75,3 +75,58 @@ def test_null_arguments(lib):
     assert lib.gapd_serve_submit(None, None, None) == -1
     lib.gapd_destroy(None)
     lib.gapd_server_destroy(None)
+
+
+def _csr(n, edges):
+    adj = [[] for _ in range(n)]
+    for u, v, w in edges:
+        adj[u].append((v, w))
+        adj[v].append((u, w))
+    rp = np.zeros(n + 1, np.int64)
+    ci, cw = [], []
+    for u in range(n):
+        for v, w in sorted(adj[u]):
+            ci.append(v)
+            cw.append(w)
+        rp[u + 1] = len(ci)
+    return rp, np.array(ci, np.int32), np.array(cw, np.int32)
+
+
+@pytest.mark.parametrize("case", ["asymmetric", "missing_reverse", "self_loop", "zero_weight", "duplicate",
+                                  "disconnected", "out_of_range", "too_many", "empty", "no_boundary", "range"])
+def test_graph_create_rejects_bad_graphs(lib, case):
+    """gapd_graph_create checks the CSR graph on the host before any device
+    call: these all fail with GAPD_EINVAL (or GAPD_ERANGE) and a message."""
+    rp, ci, cw = _csr(4, [(0, 1, 2), (1, 2, 3), (2, 3, 4)])
+    ci, cw, bnd, want = ci.copy(), cw.copy(), None, -1
+    if case == "asymmetric":
+        cw[0] += 1
+    elif case == "missing_reverse":
+        rp, ci, cw = np.array([0, 1, 1, 1, 1], np.int64), np.array([1], np.int32), np.array([1], np.int32)
+    elif case == "self_loop":
+        ci[0] = 0
+    elif case == "zero_weight":
+        rp, ci, cw = _csr(4, [(0, 1, 0), (1, 2, 3), (2, 3, 4)])
+    elif case == "duplicate":
+        rp, ci, cw = _csr(4, [(0, 1, 2), (0, 1, 2), (1, 2, 3), (2, 3, 4)])
+    elif case == "disconnected":
+        rp, ci, cw = _csr(4, [(0, 1, 2), (2, 3, 4)])
+    elif case == "out_of_range":
+        ci[0] = 7
+    elif case == "too_many":
+        rp, ci, cw = _csr(32769, [(i, i + 1, 1) for i in range(32768)])
+    elif case == "empty":
+        rp = np.zeros(1, np.int64)
+    elif case == "no_boundary":
+        bnd = np.zeros(4, np.uint8)
+    else:
+        rp, ci, cw = _csr(3, [(0, 1, 1 << 26), (1, 2, 1 << 26)])
+        want = -4
+    n = rp.size - 1
+    h = ctypes.c_void_p()
+    st = lib.gapd_graph_create(n, rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                               cw.ctypes.data if cw.size else None,
+                               None if bnd is None else bnd.ctypes.data, ctypes.byref(h))
+    assert st == want
+    assert not h.value
+    assert lib.gapd_graph_last_error(None)
