@@ -212,7 +212,7 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
     # rounds per propagation, over every propagation computed (setup, main
     # loop misses, speculative)
     rounds = s0.rounds / max(n_prop - hits + n_spec + 2, 1)
-    # Per-launch algorithmic work (units stated in the design doc):
+    # Per-launch algorithmic work:
     #   fill: the D entries and mask bits the whole run writes once, averaged per launch;
     #   step: |E_dir| x rounds relaxations (add + min) of one propagation.
     fill_bytes = (4.0 * N * N + N * N / 8.0) / max(n_prop, 1)
@@ -511,8 +511,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
-                                   "DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only one GPU is supported: sharding the sources over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
