@@ -1248,7 +1248,7 @@ __device__ int fill_from2(const FrState &fs, const uint32_t *pk, const uint16_t 
 // which would serialise as same-address atomics in L2, so each block sums
 // them in LDS and adds its totals once.  The source's own row becomes
 // complete: block 0 marks it.
-template <bool kLds, bool kLdsCount, bool kA2 = false>
+template <bool kLds, bool kLdsCount, bool kA2 = false, int kLanes = 256>
 __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *spk, int64_t *red, int chunk,
                               int nchunks) {
     const FrCtl *ctl = fs.ctl;
@@ -1294,7 +1294,7 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
         __syncthreads();
     }
     int64_t mine = 0;
-    for (int v = chunk * blockDim.x + threadIdx.x; v < N; v += nchunks * blockDim.x) {
+    for (int v = chunk * kLanes + threadIdx.x; threadIdx.x < kLanes && v < N; v += nchunks * kLanes) {
         if (v == s || (pk[v] & kFilledBit)) continue;
         const int n = kA2 ? fill_from2<16, kLdsCount>(fs, pk, a2, W, v, s, cnt)
                           : fill_from<16, kLdsCount>(fs, pk, W, W, v, s, cnt);
@@ -1400,7 +1400,10 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
 
 // The fill of the current step (blocks kSpecK..) beside the speculative
 // propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
-// that the longer propagations start at once).
+// that the longer propagations start at once).  With the grandparent table
+// only 128 threads of a fill block walk (all 256 stage the tables): the
+// walks then spread over twice the compute units, which pays for the extra
+// staging.
 template <int CONN, int S, bool kStageW, bool kLdsCount, bool kA2 = false>
 __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
@@ -1412,8 +1415,8 @@ __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs
     }
     const int slot = fs.ctl->tree_slot;
     const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
-    fr_fill_block<true, kLdsCount, kA2>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
-                                        gridDim.x - kSpecK);
+    fr_fill_block<true, kLdsCount, kA2, kA2 ? 128 : 256>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
+                                                         gridDim.x - kSpecK);
 }
 
 // Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
@@ -1589,10 +1592,11 @@ struct FrStep {
             const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
             const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
             if (a2 <= kMaxLds && g.N < 0xFFFF) {
+                const int blocks2 = (g.N + 127) / 128;  // 128 walking threads per block
                 if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks);
+                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
                 else
-                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks);
+                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
             } else if (2 * pk <= kMaxLds) {
                 if (lds + wbytes <= kMaxLds)
                     e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
