@@ -186,8 +186,8 @@ const char *gapd_last_error(gapd_ctx *ctx);
  * Every edge must appear in both rows with the same weight, with no self
  * loop and no repeated neighbour, and the graph must be connected, else
  * GAPD_EINVAL.  Every distance is at most the total weight of the
- * breadth-first spanning tree from vertex 0; if that reaches 2^27 the call
- * gives GAPD_ERANGE.  The arrays are copied.  gapd_last_error(NULL) explains a failed create. */
+ * breadth-first spanning tree from vertex 0; if that reaches 2^27, or any
+ * single edge weighs 2^27 or more, the call gives GAPD_ERANGE.  The arrays are copied.  gapd_last_error(NULL) explains a failed create. */
 typedef struct gapd_graph gapd_graph;
 int gapd_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const int32_t *weight,
                       const uint8_t *boundary, gapd_graph **out);
@@ -267,7 +267,10 @@ int gapd_server_create(void *arena_dev, size_t arena_bytes, int max_slots, gapd_
 int gapd_serve_submit(gapd_server *srv, const gapd_job *job, uint64_t *ticket);
 
 /* GAPD_PENDING while queued or running, GAPD_OK with *res filled when done
- * (the result stays valid until gapd_serve_release), or the job's error. */
+ * (the result stays valid until gapd_serve_release), or the job's error.  A
+ * job is marked done or failed only once its slot's stream has drained.  A
+ * device error fails that job with GAPD_EDEVICE and poisons the server: every
+ * job admitted after it fails with GAPD_EDEVICE too. */
 int gapd_serve_poll(gapd_server *srv, uint64_t ticket, gapd_result *res);
 
 /* Block until the job is done (or failed); same results as gapd_serve_poll. */

@@ -33,6 +33,11 @@ int validate_graph(int64_t n, const int64_t *rp, const int32_t *ci, const int32_
             if (u < 0 || u >= n) { why = "a neighbour id is out of range"; return GAPD_EINVAL; }
             if (u == v) { why = "a self loop"; return GAPD_EINVAL; }
             if (cw[e] < 1) { why = "an edge weight is below 1"; return GAPD_EINVAL; }
+            // No distance may reach 2^27 (the tree words keep 5 flag bits
+            // above it), and the kernels add a weight to a distance in int32:
+            // an edge at least that heavy is refused even off the spanning
+            // tree checked below.
+            if (cw[e] >= kDistLimit) { why = "an edge weighs 2^27 or more"; return GAPD_ERANGE; }
             if (mark[u] == v) { why = "a neighbour is listed twice"; return GAPD_EINVAL; }
             mark[u] = v;
         }

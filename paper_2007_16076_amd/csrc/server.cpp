@@ -6,6 +6,7 @@
 // jobs run concurrently, one HIP stream per slot, so work from different
 // requests overlaps on the device.  A finished job keeps its result in the
 // arena until gapd_serve_release returns the bytes, which lets waiting jobs in.
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -113,6 +114,7 @@ struct gapd_server {
     std::map<uint64_t, std::unique_ptr<JobRec>> jobs;
     uint64_t next_ticket = 1;
     bool stop = false;
+    std::atomic<bool> poisoned{false};  // a device error happened: no more jobs run
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -194,7 +196,15 @@ void gapd_server::worker_loop() {
             }
             if (!j) break;
         }
-        const int r = run_job(*j, st);
+        int r = poisoned.load() ? GAPD_EDEVICE : run_job(*j, st);
+        // Whatever run_job returned, nothing of this job may still be queued
+        // on the slot's stream once its arena range can be released.  A device
+        // error poisons the server: every later job fails at once.
+        const hipError_t se = hipStreamSynchronize(st);
+        if (se != hipSuccess || r == GAPD_EDEVICE) {
+            poisoned.store(true);
+            r = GAPD_EDEVICE;
+        }
         {
             std::lock_guard<std::mutex> lk(mu);
             j->t_done = now();

@@ -93,7 +93,8 @@ def _csr(n, edges):
 
 
 @pytest.mark.parametrize("case", ["asymmetric", "missing_reverse", "self_loop", "zero_weight", "duplicate",
-                                  "disconnected", "out_of_range", "too_many", "empty", "no_boundary", "range"])
+                                  "disconnected", "out_of_range", "too_many", "empty", "no_boundary", "range",
+                                  "heavy_edge"])
 def test_graph_create_rejects_bad_graphs(lib, case):
     """gapd_graph_create checks the CSR graph on the host before any device
     call: these all fail with GAPD_EINVAL (or GAPD_ERANGE) and a message."""
@@ -119,6 +120,12 @@ def test_graph_create_rejects_bad_graphs(lib, case):
         rp = np.zeros(1, np.int64)
     elif case == "no_boundary":
         bnd = np.zeros(4, np.uint8)
+    elif case == "heavy_edge":
+        # triangle 0-1 (1), 1-2 (1), 0-2 (2^31 - 1): the breadth-first tree from 0
+        # takes 0-1 and 0-2, so only a per-edge bound catches the heavy edge,
+        # whose weight added to a distance would wrap in int32
+        rp, ci, cw = _csr(3, [(0, 1, 1), (1, 2, 1), (0, 2, 2**31 - 1)])
+        want = -4
     else:
         rp, ci, cw = _csr(3, [(0, 1, 1 << 26), (1, 2, 1 << 26)])
         want = -4
