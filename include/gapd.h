@@ -138,7 +138,9 @@ int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out);
  * int32.  mode GAPD_MODE_NAIVE runs N propagations; GAPD_MODE_TREE_FILL_FR
  * runs the filling-rate method, GAPD_MODE_TREE_FILL_EXTREMA the geodesic
  * extrema method; both need the workspace.  All give the same, unique D
- * (Section 2, Property 1).  GAPD_MODE_TREE_FILL_SPIRAL is refused here
+ * (Section 2, Property 1).  The tree modes need H <= 192 and W <= 192 (their
+ * propagation keeps the distance field in LDS), else GAPD_EINVAL.
+ * GAPD_MODE_TREE_FILL_SPIRAL is refused here
  * (GAPD_EINVAL): it needs draws.  st: nullable host struct.  Returns when the
  * result is complete on the stream (the call synchronises the stream). */
 int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
@@ -157,7 +159,8 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
  *   draws  DEVICE pointer to N uniform uint32 draws, caller-owned, read only
  *          (N always suffice: every propagation completes its source's row)
  *   out    DEVICE pointer to N*N int32
- * Needs the workspace of gapd_workspace_size(GAPD_MODE_TREE_FILL_SPIRAL).
+ * Needs the workspace of gapd_workspace_size(GAPD_MODE_TREE_FILL_SPIRAL), and
+ * H <= 192 and W <= 192 (GAPD_EINVAL otherwise).
  * No setup propagations (st->n_prop_setup = 0, st->centroid = -1). */
 int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *out, gapd_stats *st);
 

@@ -15,7 +15,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgapd.so")
-SOURCES = ["kernels.hip", "capi.cpp", "server.cpp", "graph.cpp"]
+# (source, object, extra flags).  k_fr.hip is compiled once per (connectivity,
+# size class) pair so its template instantiations build in parallel.
+FR_PARTS = [(c, s) for c in (4, 8) for s in (32, 64, 128, 192)]
+UNITS = [("k_fr.hip", f"k_fr_{c}_{s}", [f"-DGAPD_CONN={c}", f"-DGAPD_S={s}"]) for c, s in FR_PARTS] + \
+        [(f, f.rsplit(".", 1)[0], []) for f in
+         ("k_misc.hip", "k_naive.hip", "k_frb.hip", "k_graph.hip", "capi.cpp", "server.cpp", "graph.cpp")]
 ARCH = os.environ.get("GAPD_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,13 +40,13 @@ def flags():
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs, procs = [], []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
-        cmd = [hipcc()] + flags() + (["-x", "hip"] if src.endswith(".cpp") else []) + \
+    for src, name, extra in UNITS:
+        obj = os.path.join(BUILD, name + ".o")
+        cmd = [hipcc()] + flags() + extra + (["-x", "hip"] if src.endswith(".cpp") else []) + \
               ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        procs.append((name, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     failed = []
     for src, p in procs:

@@ -232,6 +232,8 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = ctx->N;
     } else {
+        if (!tree_methods_fit(ctx->H, ctx->W))
+            return fail(ctx, GAPD_EINVAL, "the tree methods need both image sides <= 192 (distance field in LDS)");
         const size_t need = fr_workspace_bytes(ctx->N, true);
         if (!ctx->ws || ctx->ws_bytes < need) return fail(ctx, GAPD_ENOMEM, "tree-method workspace missing or too small");
         FrState fs = fr_workspace_layout(ctx->ws, ctx->N, true);

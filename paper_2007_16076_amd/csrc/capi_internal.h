@@ -13,6 +13,11 @@ int env_int(const char *name, int dflt);
 int validate_image(const uint8_t *img, int H, int W, int C, int conn, int wmode, std::string &why);
 int max_rounds_for(int N);
 
+// Longest image side the tree-based methods accept on one image: their step
+// kernel keeps the distance field in LDS.
+constexpr int kTreeMaxSide = 192;
+inline bool tree_methods_fit(int H, int W) { return H <= kTreeMaxSide && W <= kTreeMaxSide; }
+
 // Propagations from K sources into K rows of out; synchronises the stream.
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
              hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr,

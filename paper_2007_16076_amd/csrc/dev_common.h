@@ -1,26 +1,18 @@
-// HIP kernels of libgapd.so for gfx950 (CDNA4, wave64).
-//
-// The hot path of the filling-rate method (Noyel, Angulo, Jeulin, "Fast
-// computation of all pairs of geodesic distances", Section 3.4, algorithm
-// "filling") and of the naive method (Section 1):
-//   * k_prep / k_prefix   edge weights of the pseudo-metric (Section 2, eq.
-//                         distance_somme; 1 + L1 for multiband images) and
-//                         running sums along rows and columns;
-//   * relax_block         one geodesic propagation (Section 2, eqs. temps and
-//                         distance: minimum over paths of summed weights),
-//                         computed as the fixed point of min-plus relaxation
-//                         with the distance field resident in LDS;
-//   * parent_code         the geodesic tree (Section 2): each pixel's parent
-//                         is the smallest-index tight neighbour;
-//   * k_fr_step           least-filled source selection (Section 3.4) +
-//                         propagation + tree, for one step;
-//   * k_fr_fill           redundancy fill along the tree (Property 1):
-//                         d(u,v) = d(s,v) - d(s,u) for every ancestor u of v;
-//   * k_fr_setup / k_rank geodesic centroid and extrema ranks (Section 3.3).
+// Device code shared by the HIP translation units of libgapd.so (gfx950,
+// CDNA4, wave64): edge weights of the pseudo-metric (Section 2, eq.
+// distance_somme; 1 + L1 for multiband images), geodesic propagation as the
+// fixed point of min-plus sweeps in LDS (Section 2, eqs. temps and distance),
+// the geodesic tree (each pixel's parent is its smallest-index tight
+// neighbour), the source-selection rules (Sections 3.1-3.4) and the
+// redundancy fill along a tree (Property 1).  Everything here has internal
+// linkage; each translation unit instantiates what its kernels use.
 //
 // No MFMA: the work is integer min-plus, not a dense contraction.
+#pragma once
 #include "gapd_internal.h"
 #include "gapd.h"
+
+#pragma clang diagnostic ignored "-Wunused-function"
 
 namespace gapd {
 
@@ -84,9 +76,6 @@ __device__ void prep_pixels(const GImgW &w, const uint8_t *img, int C, int wmode
     }
 }
 
-__global__ void k_prep(GImgW w, const uint8_t *img, int C, int wmode) {
-    prep_pixels(w, img, C, wmode, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
 
 __device__ void prefix_lines(const GImgW &w, int t0, int stride) {
     const int H = w.H, W = w.W;
@@ -102,18 +91,6 @@ __device__ void prefix_lines(const GImgW &w, int t0, int stride) {
     }
 }
 
-__global__ void k_prefix(GImgW w) { prefix_lines(w, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x); }
-
-__global__ void k_prep_batched(const GImgW *ws, const uint8_t *imgs, const int64_t *img_off, int C, int wmode) {
-    const GImgW w = ws[blockIdx.y];
-    prep_pixels(w, imgs + img_off[blockIdx.y], C, wmode, blockIdx.x * blockDim.x + threadIdx.x,
-                gridDim.x * blockDim.x);
-}
-
-__global__ void k_prefix_batched(const GImgW *ws) {
-    const GImgW w = ws[blockIdx.x];
-    prefix_lines(w, threadIdx.x, blockDim.x);
-}
 
 // ---------------------------------------------------------------------------------------------
 // Wave-level min scans over 64 lanes (DPP row shifts inside each 16-lane row,
@@ -498,39 +475,6 @@ __device__ int64_t block_sum_i64(int64_t v, int64_t *red) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Naive method / multi-source propagations: block b propagates from
-// src_list[b] (or src_base + b) and writes row b of out (Section 1).
-// With kGlobal the distance field lives in the output row itself (images too
-// large for LDS); otherwise in LDS, and the row is written once at the end.
-// ---------------------------------------------------------------------------------------------
-template <int CONN, int S, bool kGlobal>
-__global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, const int32_t *src_list,
-                                                              int src_base, int32_t *out, int max_rounds,
-                                                              FrCtl *ctl) {
-    extern __shared__ int smem[];
-    const int s = src_list ? src_list[blockIdx.x] : src_base + (int)blockIdx.x;
-    int32_t *row = out + (size_t)blockIdx.x * g.N;
-    int *d = kGlobal ? row : smem;
-    const int Wd = kGlobal ? g.W : Wp;
-    fill_inf(d, g.H * Wd);
-    __syncthreads();
-    if (threadIdx.x == 0) d[(s / g.W) * Wd + s % g.W] = 0;
-    __syncthreads();
-    const int r = relax_block<CONN, S, kGlobal>(g, d, Wd, max_rounds);
-    if (threadIdx.x == 0) {
-        if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
-        atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
-    }
-    if (!kGlobal) {
-        const uint64_t mW = divw_magic(g.W);
-        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = divw(v, mW), x = v - y * g.W;
-            row[v] = d[y * Wp + x];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
 // Filling-rate method, one image.
 // ---------------------------------------------------------------------------------------------
 
@@ -551,12 +495,6 @@ __device__ void fr_init_range(const FrState &fs, int i0, int stride) {
         fs.D[(size_t)i * fs.N + i] = 0;
         if ((i & 31) == 0) fs.full[i >> 5] = fs.N == 1 ? 1u : 0u;
     }
-}
-
-__global__ void k_fr_init(FrState fs) { fr_init_range(fs, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x); }
-
-__global__ void k_fr_init_b(const BImg *imgs) {
-    fr_init_range(imgs[blockIdx.y].fr, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // count[i] += inc, keeping the complete-row bitmap in step: the addition
@@ -606,21 +544,6 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
     }
 }
 
-template <int CONN, int S>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_setup(GImg g, int Wp, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    fr_setup_block<CONN, S>(g, Wp, fs, smem, max_rounds, red);
-}
-
-template <int CONN, int S>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_setup_b(const BImg *imgs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    const BImg &bi = imgs[blockIdx.x];
-    fr_setup_block<CONN, S>(bi.g, bi.Wp, bi.fr, smem, max_rounds, red);
-}
-
 // rank[x] = position of x in the list sorted by decreasing d_c, ties by
 // increasing index (Section 3.3); order = inverse permutation.  Brute-force
 // counting over all pairs (N^2 comparisons, once per run).
@@ -644,13 +567,6 @@ __device__ void rank_block(const int32_t *dc, int N, int32_t *rank, int32_t *ord
 __global__ void k_rank(const int32_t *dc, int N, int32_t *rank, int32_t *order) {
     __shared__ int32_t tile[256];
     rank_block(dc, N, rank, order, tile);
-}
-
-__global__ void k_rank_b(const BImg *imgs) {
-    __shared__ int32_t tile[256];
-    const FrState &fs = imgs[blockIdx.y].fr;
-    if ((int)(blockIdx.x * blockDim.x) >= fs.N) return;
-    rank_block(fs.dbuf, fs.N, fs.rank, fs.order, tile);
 }
 
 // Least filled point (Section 3.4): argmin over x of (count[x], rank[x]).
@@ -1072,34 +988,6 @@ __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_
     }
 }
 
-template <int CONN, int S, bool kStageW>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    fr_step_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, red, nullptr);
-}
-
-// Static LDS of the speculation plan's sort keys (beyond the usual reserve).
-constexpr size_t kSpecSortLds = (2 * kRelaxThreads + kSpecSlots) * sizeof(uint64_t);
-
-template <int CONN, int S, bool kStageW>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    __shared__ uint64_t keys[2 * kRelaxThreads];
-    __shared__ uint64_t skeys[kSpecSlots];
-    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys);
-}
-
-// Every image of a batch takes its step at once: block b is image b.
-template <int CONN, int S, bool kStageW>
-__global__ __launch_bounds__(kRelaxThreads) void k_fr_step_b(const BImg *imgs, int max_rounds, int *batch_done) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    const BImg &bi = imgs[blockIdx.x];
-    fr_step_block<CONN, S, kStageW>(bi.g, bi.Wp, bi.fr, max_rounds, smem, red, batch_done);
-}
-
 // Redundancy fill for pixel v along its ancestors (Property 1): every
 // ancestor u on the tree path from the source gives d(u,v) = d(s,v) - d(s,u).
 // pk holds the tree words with row stride pkW (W for global arrays, Wp for
@@ -1321,13 +1209,6 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
     }
 }
 
-template <bool kLds, bool kLdsCount>
-__global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
-    extern __shared__ uint32_t spk[];
-    __shared__ int64_t red[4];
-    fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
-}
-
 // Piece j of the speculation plan, one round of a propagation into its
 // cache slot: a new candidate starts in its victim slot (source at 0, the
 // rest infinite), a running one resumes from the partial distance field kept
@@ -1398,38 +1279,6 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
     if (threadIdx.x == 0) atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
 }
 
-// The fill of the current step (blocks kSpecK..) beside the speculative
-// propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
-// that the longer propagations start at once).  With the grandparent table
-// only 128 threads of a fill block walk (all 256 stage the tables): the
-// walks then spread over twice the compute units, which pays for the extra
-// staging.
-template <int CONN, int S, bool kStageW, bool kLdsCount, bool kA2 = false>
-__global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ int64_t red[4];
-    if (fs.ctl->done) return;
-    if ((int)blockIdx.x < kSpecK) {
-        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, smem, blockIdx.x);
-        return;
-    }
-    const int slot = fs.ctl->tree_slot;
-    const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
-    fr_fill_block<true, kLdsCount, kA2, kA2 ? 128 : 256>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
-                                                         gridDim.x - kSpecK);
-}
-
-// Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
-template <bool kLds, bool kLdsCount>
-__global__ __launch_bounds__(256) void k_fr_fill_b(const BImg *imgs) {
-    extern __shared__ uint32_t spk[];
-    __shared__ int64_t red[4];
-    const BImg &bi = imgs[blockIdx.y];
-    if ((int)(blockIdx.x * blockDim.x) >= bi.fr.N) return;
-    fr_fill_block<kLds, kLdsCount>(bi.fr, bi.fr.packed, bi.g.W, spk, red, blockIdx.x,
-                                   (bi.fr.N + blockDim.x - 1) / blockDim.x);
-}
-
 // ---------------------------------------------------------------------------------------------
 // Batched: naive over every (image, source) item, one block per item.
 // ---------------------------------------------------------------------------------------------
@@ -1440,35 +1289,6 @@ __device__ int find_image(const BImg *imgs, int B, int64_t item) {
         if (imgs[mid].item0 <= item) lo = mid; else hi = mid - 1;
     }
     return lo;
-}
-
-template <int CONN, int S>
-__global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg *imgs, int B, int32_t *out,
-                                                                      int max_rounds, FrCtl *ctl) {
-    extern __shared__ int smem[];
-    const int64_t item = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
-    const int b = find_image(imgs, B, item);
-    const BImg &bi = imgs[b];
-    const GImg g = bi.g;
-    const int s = (int)(item - bi.item0);
-    if (s >= g.N) return;  // padding items of the 2-D grid
-    const int Wp = bi.Wp;
-    int *d = smem;
-    fill_inf(d, g.H * Wp);
-    __syncthreads();
-    if (threadIdx.x == 0) d[(s / g.W) * Wp + s % g.W] = 0;
-    __syncthreads();
-    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
-    if (threadIdx.x == 0) {
-        if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
-        atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
-    }
-    int32_t *row = out + bi.out_off + (size_t)s * g.N;
-    const uint64_t mW = divw_magic(g.W);
-    for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-        const int y = divw(v, mW), x = v - y * g.W;
-        row[v] = d[y * Wp + x];
-    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1513,636 +1333,6 @@ hipError_t set_lds(K kernel, size_t bytes) {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int CONN, int S>
-struct RelaxRows {
-    static hipError_t run(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                          int max_rounds, FrCtl *ctl, hipStream_t st) {
-        const int Wp = lds_row_stride(g.W);
-        const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        if (lds <= kMaxLds) {
-            auto k = k_relax_rows<CONN, S, false>;
-            hipError_t e = set_lds(k, lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k, dim3(K), dim3(kRelaxThreads), lds, st, g, Wp, src_list, src_base, out,
-                               max_rounds, ctl);
-        } else {
-            hipLaunchKernelGGL((k_relax_rows<CONN, S, true>), dim3(K), dim3(kRelaxThreads), 0, st, g, g.W,
-                               src_list, src_base, out, max_rounds, ctl);
-        }
-        return hipGetLastError();
-    }
-};
-
-template <int CONN, int S>
-struct FrSetup {
-    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
-        const int Wp = lds_row_stride(g.W);
-        const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        auto k1 = k_fr_setup<CONN, S>;
-        hipError_t e = set_lds(k1, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
-        hipLaunchKernelGGL(k_rank, dim3((g.N + 255) / 256), dim3(256), 0, st, fs.dbuf, g.N, fs.rank, fs.order);
-        return hipGetLastError();
-    }
-};
-
-template <int CONN, int S>
-struct FrStep {
-    template <bool kStageW, bool kLdsCount, bool kA2 = false>
-    static hipError_t launch_fill_spec(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
-                                       size_t lds, int blocks) {
-        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount, kA2>;
-        hipError_t e = set_lds(k, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(kSpecK + blocks), dim3(256), lds, st, g, Wp, fs, max_rounds);
-        return hipGetLastError();
-    }
-
-    template <bool kStageW>
-    static hipError_t launch_step(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
-                                  size_t lds, bool spec) {
-        auto k1 = spec ? k_fr_step_spec<CONN, S, kStageW> : k_fr_step<CONN, S, kStageW>;
-        hipError_t e = set_lds(k1, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
-        return hipGetLastError();
-    }
-
-    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
-        const int Wp = lds_row_stride(g.W);
-        const size_t lds = (size_t)g.H * Wp * sizeof(int);
-        const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
-        const size_t pk = (size_t)g.N * sizeof(uint32_t);
-        // speculation needs the fill to stage a tree in LDS and the select
-        // kernel to hold its sort keys beside the field
-        const bool spec = fs.cache && pk <= kMaxLds && lds + kSpecSortLds <= kMaxLds;
-        const size_t extra = spec ? kSpecSortLds : 0;
-        hipError_t e = lds + wbytes + extra <= kMaxLds
-                           ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes, spec)
-                           : launch_step<false>(g, Wp, fs, max_rounds, st, lds, spec);
-        if (e != hipSuccess) return e;
-        if (mid) {
-            e = hipEventRecord(mid, st);
-            if (e != hipSuccess) return e;
-        }
-        const int blocks = (g.N + 255) / 256;
-        if (spec) {
-            // the fill beside the speculative propagations
-            const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
-            const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
-            if (a2 <= kMaxLds && g.N < 0xFFFF) {
-                const int blocks2 = (g.N + 127) / 128;  // 128 walking threads per block
-                if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
-                else
-                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
-            } else if (2 * pk <= kMaxLds) {
-                if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
-                else
-                    e = launch_fill_spec<false, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
-            } else {
-                if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
-                else
-                    e = launch_fill_spec<false, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
-            }
-            if (e != hipSuccess) return e;
-        } else if (2 * pk <= kMaxLds) {
-            auto k2 = k_fr_fill<true, true>;
-            e = set_lds(k2, 2 * pk);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), 2 * pk, st, fs, g.W);
-        } else if (pk <= kMaxLds) {
-            auto k2 = k_fr_fill<true, false>;
-            e = set_lds(k2, pk);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), pk, st, fs, g.W);
-        } else {
-            hipLaunchKernelGGL((k_fr_fill<false, false>), dim3(blocks), dim3(256), 0, st, fs, g.W);
-        }
-        return hipGetLastError();
-    }
-};
-
-template <int CONN, int S>
-struct RelaxRowsBatched {
-    static hipError_t run(const BImg *imgs, int B, int64_t n_items, size_t lds, int32_t *out, int max_rounds,
-                          FrCtl *ctl, hipStream_t st) {
-        auto k = k_relax_rows_batched<CONN, S>;
-        hipError_t e = set_lds(k, lds);
-        if (e != hipSuccess) return e;
-        const int64_t gx = n_items < 65536 ? n_items : 65536;
-        const int64_t gy = (n_items + gx - 1) / gx;
-        hipLaunchKernelGGL(k, dim3((unsigned)gx, (unsigned)gy), dim3(kRelaxThreads), lds, st, imgs, B, out,
-                           max_rounds, ctl);
-        return hipGetLastError();
-    }
-};
-
-template <int CONN, int S>
-struct FrBatchedSetup {
-    static hipError_t run(const BImg *imgs, int B, int maxN, size_t lds, int max_rounds, hipStream_t st) {
-        hipLaunchKernelGGL(k_fr_init_b, dim3((maxN + 255) / 256, B), dim3(256), 0, st, imgs);
-        auto k = k_fr_setup_b<CONN, S>;
-        hipError_t e = set_lds(k, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(B), dim3(kRelaxThreads), lds, st, imgs, max_rounds);
-        hipLaunchKernelGGL(k_rank_b, dim3((maxN + 255) / 256, B), dim3(256), 0, st, imgs);
-        return hipGetLastError();
-    }
-};
-
-template <int CONN, int S>
-struct FrBatchedStep {
-    static hipError_t run(const BImg *imgs, int B, int maxN, size_t lds, size_t wbytes, int max_rounds,
-                          int *batch_done, hipStream_t st) {
-        hipError_t e;
-        if (lds + wbytes <= kMaxLds) {
-            auto k1 = k_fr_step_b<CONN, S, true>;
-            e = set_lds(k1, lds + wbytes);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k1, dim3(B), dim3(kRelaxThreads), lds + wbytes, st, imgs, max_rounds, batch_done);
-        } else {
-            auto k1 = k_fr_step_b<CONN, S, false>;
-            e = set_lds(k1, lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k1, dim3(B), dim3(kRelaxThreads), lds, st, imgs, max_rounds, batch_done);
-        }
-        const size_t pk = (size_t)maxN * sizeof(uint32_t);
-        const dim3 grid((maxN + 255) / 256, B);
-        if (2 * pk <= kMaxLds) {
-            auto k2 = k_fr_fill_b<true, true>;
-            e = set_lds(k2, 2 * pk);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k2, grid, dim3(256), 2 * pk, st, imgs);
-        } else if (pk <= kMaxLds) {
-            auto k2 = k_fr_fill_b<true, false>;
-            e = set_lds(k2, pk);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k2, grid, dim3(256), pk, st, imgs);
-        } else {
-            hipLaunchKernelGGL((k_fr_fill_b<false, false>), grid, dim3(256), 0, st, imgs);
-        }
-        return hipGetLastError();
-    }
-};
-
-// ---------------------------------------------------------------------------------------------
-// General graphs (Section 5): the same propagations, trees, fill and
-// selection rules on an undirected CSR graph.
-// ---------------------------------------------------------------------------------------------
-
-// Frontier list capacity of a graph propagation: what LDS holds beside the
-// n distances and the two frontier bitmaps, at most 8192 entries.
-__host__ __device__ inline int graph_list_cap(int n) {
-    const long long rest = (long long)kMaxLds - 4ll * n - 8ll * ((n + 31) / 32);
-    return (int)(rest / 4 < 8192 ? rest / 4 : 8192);
-}
-
-__host__ __device__ inline size_t graph_prop_lds(int n) {
-    return (size_t)n * 4 + 8 * (size_t)((n + 31) / 32) + 4 * (size_t)graph_list_cap(n);
-}
-
-// LDS of a graph propagation: n distances, two frontier bitmaps, the list.
-struct GFront {
-    uint32_t *cur, *nxt;
-    int *list;
-    int cap;
-};
-
-__device__ __forceinline__ GFront graph_lds(int n, int *smem, int *&d) {
-    const int nw = (n + 31) >> 5;
-    GFront f;
-    d = smem;
-    f.cur = (uint32_t *)(smem + n);
-    f.nxt = f.cur + nw;
-    f.list = (int *)(f.nxt + nw);
-    f.cap = graph_list_cap(n);
-    return f;
-}
-
-// Relax the edges of v (distance dv) in rows e0..e1, 8 edge loads in flight;
-// improved vertices join the next frontier.
-__device__ __forceinline__ void graph_relax_edges(const GGraph &g, int *d, uint32_t *nxt, int dv, int64_t e0,
-                                                  int64_t e1, int &any) {
-    for (int64_t e = e0; e < e1; e += 8) {
-        int u[8], w[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t ee = e + k < e1 ? e + k : e1 - 1;  // a repeated edge relaxes nothing new
-            u[k] = g.ci[ee];
-            w[k] = g.cw[ee];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int nd = dv + w[k];
-            if (nd < d[u[k]] && nd < atomicMin(&d[u[k]], nd)) {
-                atomicOr(&nxt[u[k] >> 5], 1u << (u[k] & 31));
-                any = 1;
-            }
-        }
-    }
-}
-
-// One propagation on a CSR graph by a frontier Bellman-Ford in LDS: every
-// vertex whose distance dropped in the last round relaxes its edges (LDS
-// atomic minimums; a vertex that improves joins the next frontier).  d and
-// the bitmap f.cur hold the seeds on entry; f.nxt is zero.  Positive weights
-// end it within n rounds.  Returns the rounds, or -1 at the cap.  Each round
-// compacts the frontier into an LDS list (in passes of at most f.cap
-// vertices) so that the threads share it evenly.
-__device__ int graph_relax_block(const GGraph &g, int *d, GFront f, int max_rounds, int64_t *red) {
-    const int nw = (g.n + 31) >> 5;
-    for (int r = 1; r <= max_rounds; ++r) {
-        int any = 0;
-        for (;;) {
-            int c = 0;
-            for (int w = threadIdx.x; w < nw; w += blockDim.x) c += __popc(f.cur[w]);
-            int total;
-            int pos = block_excl_scan(c, red, &total);
-            if (total == 0) break;
-            for (int w = threadIdx.x; w < nw && pos < f.cap; w += blockDim.x) {
-                uint32_t b = f.cur[w];
-                while (b && pos < f.cap) {
-                    f.list[pos++] = (w << 5) + __ffs(b) - 1;
-                    b &= b - 1;
-                }
-                f.cur[w] = b;  // what did not fit waits for the next pass
-            }
-            __syncthreads();
-            const int F = total < f.cap ? total : f.cap;
-            for (int i = threadIdx.x; i < F; i += blockDim.x) {
-                const int v = f.list[i];
-                graph_relax_edges(g, d, f.nxt, d[v], g.rp[v], g.rp[v + 1], any);
-            }
-            __syncthreads();
-            if (total <= f.cap) break;  // the whole frontier was listed
-        }
-        if (!__syncthreads_or(any)) return r;
-        uint32_t *t = f.cur;
-        f.cur = f.nxt;
-        f.nxt = t;
-    }
-    return -1;
-}
-
-// d = INF, frontiers empty; then the seeds (seed < 0: the boundary vertices).
-__device__ void graph_seed(const GGraph &g, int *d, const GFront &f, int seed) {
-    const int nw = (g.n + 31) >> 5;
-    for (int v = threadIdx.x; v < g.n; v += blockDim.x) d[v] = kInf;
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) { f.cur[w] = 0; f.nxt[w] = 0; }
-    __syncthreads();
-    if (seed >= 0) {
-        if (threadIdx.x == 0) { d[seed] = 0; f.cur[seed >> 5] = 1u << (seed & 31); }
-    } else {
-        for (int v = threadIdx.x; v < g.n; v += blockDim.x)
-            if (g.bnd[v]) { d[v] = 0; atomicOr(&f.cur[v >> 5], 1u << (v & 31)); }
-    }
-    __syncthreads();
-}
-
-// Block b propagates from src_list[b] (or src_base + b) and writes row b.
-__global__ __launch_bounds__(kRelaxThreads) void k_graph_rows(GGraph g, const int32_t *src_list, int src_base,
-                                                             int32_t *out, int max_rounds, FrCtl *ctl) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    int *d;
-    const GFront f = graph_lds(g.n, smem, d);
-    const int s = src_list ? src_list[blockIdx.x] : src_base + (int)blockIdx.x;
-    graph_seed(g, d, f, s);
-    const int r = graph_relax_block(g, d, f, max_rounds, (int64_t *)red);
-    int32_t *row = out + (size_t)blockIdx.x * g.n;
-    for (int v = threadIdx.x; v < g.n; v += blockDim.x) row[v] = d[v];
-    if (threadIdx.x == 0) {
-        if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
-        atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
-    }
-}
-
-// Geodesic centre and extrema of a graph (Section 5): propagate from the
-// boundary vertices, take the first vertex of maximal distance, propagate
-// from it into fs.dbuf.  One block.
-__global__ __launch_bounds__(kRelaxThreads) void k_graph_setup(GGraph g, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    int *d;
-    const GFront f = graph_lds(g.n, smem, d);
-    graph_seed(g, d, f, -1);
-    const int r1 = graph_relax_block(g, d, f, max_rounds, (int64_t *)red);
-    uint64_t best = ~0ull;
-    for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
-        const uint64_t key = ((uint64_t)(uint32_t)(kInf - d[v]) << 32) | (uint32_t)v;
-        best = key < best ? key : best;
-    }
-    best = block_min_u64(best, red);
-    const int c = (int)(best & 0xFFFFFFFFu);
-    graph_seed(g, d, f, c);
-    const int r2 = graph_relax_block(g, d, f, max_rounds, (int64_t *)red);
-    for (int v = threadIdx.x; v < g.n; v += blockDim.x) fs.dbuf[v] = d[v];
-    if (threadIdx.x == 0) {
-        fs.ctl->centroid = c;
-        if (r1 < 0 || r2 < 0) fs.ctl->err = GAPD_ENOCONV;
-        fs.ctl->rounds += (r1 < 0 ? max_rounds : r1) + (r2 < 0 ? max_rounds : r2);
-    }
-}
-
-// Select by the filling-rate or extrema rule, propagate from the source and
-// write the tree entries: parent = the smallest-index neighbour q with
-// d(q) + w(q,v) = d(v), from the final distances.  One block.
-__global__ __launch_bounds__(kRelaxThreads) void k_graph_step(GGraph g, FrState fs, int max_rounds) {
-    extern __shared__ int smem[];
-    __shared__ uint64_t red[kRelaxThreads / 64];
-    FrCtl *ctl = fs.ctl;
-    if (ctl->done) return;
-    if (threadIdx.x == 0 && fs.filled_out && ctl->n_prop > 0) fs.filled_out[ctl->n_prop - 1] = ctl->filled;
-    const int s = fs.rule == kRuleExtrema ? fr_select<kRuleExtrema>(fs, red) : fr_select<kRuleFilling>(fs, red);
-    if (s < 0) {
-        if (threadIdx.x == 0) ctl->done = 1;
-        return;
-    }
-    if (threadIdx.x == 0) {
-        if (fs.seq_out) fs.seq_out[ctl->n_prop] = s;
-        ctl->s = s;
-        ctl->n_prop += 1;
-    }
-    int *d;
-    const GFront f = graph_lds(g.n, smem, d);
-    graph_seed(g, d, f, s);
-    const int r = graph_relax_block(g, d, f, max_rounds, (int64_t *)red);
-    for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
-        const int dv = d[v];
-        uint32_t par = 0xFFFFFFFFu;
-        if (v != s) {
-            const int64_t e1 = g.rp[v + 1];
-            for (int64_t e = g.rp[v]; e < e1; ++e) {
-                const int q = g.ci[e];
-                if (d[q] + g.cw[e] == dv && (uint32_t)q < par) par = (uint32_t)q;
-            }
-        }
-        fs.gtree[v] = ((uint64_t)(uint32_t)dv << 32) | par;
-    }
-    if (threadIdx.x == 0) {
-        if (r < 0) ctl->err = GAPD_ENOCONV;
-        ctl->rounds += r < 0 ? max_rounds : r;
-    }
-}
-
-// Tree entry helpers: distance in bits 32..61, complete-row flag in bit 62
-// (set only on the LDS copy), parent in the low 32 bits (-1 at the root).
-constexpr uint64_t kGFilled = 1ull << 62;
-__device__ __forceinline__ int gt_dist(uint64_t t) { return (int)((t >> 32) & 0x3FFFFFFFu); }
-__device__ __forceinline__ int gt_parent(uint64_t t) { return (int)(uint32_t)t; }
-
-// Redundancy fill for vertex v along its ancestors (Property 1), as
-// fill_from, with the parent read from the tree entry.  Without the LDS copy
-// an ancestor's complete row is read from the bitmap (never the source's:
-// block 0 marks it complete while other blocks may still walk).
-template <bool kLds, bool kCntLds>
-__device__ int graph_fill_from(const FrState &fs, const uint64_t *tr, int v, int s, int *cnt) {
-    const int N = fs.N, MW = fs.MW;
-    const uint64_t tv = tr[v];
-    const int dv = gt_dist(tv);
-    uint32_t *mrow = fs.mask + (size_t)v * MW;
-    int32_t *Drow = fs.D + (size_t)v * N;
-    int nnew = 0;
-    for (int u = gt_parent(tv); u >= 0;) {
-        const uint64_t tu = tr[u];
-        const bool complete = kLds ? (tu & kGFilled) != 0 : (u != s && ((fs.full[u >> 5] >> (u & 31)) & 1u));
-        if (!complete && !((mrow[u >> 5] >> (u & 31)) & 1u)) {
-            const int val = dv - gt_dist(tu);
-            Drow[u] = val;
-            fs.D[(size_t)u * N + v] = val;
-            atomicOr(&mrow[u >> 5], 1u << (u & 31));
-            if (u != s) {
-                atomicOr(&fs.mask[(size_t)u * MW + (v >> 5)], 1u << (v & 31));
-                if (kCntLds)
-                    atomicAdd(&cnt[u], 1);
-                else
-                    count_add(fs, u, 1);
-            }
-            ++nnew;
-        }
-        u = gt_parent(tu);
-    }
-    return nnew;
-}
-
-template <bool kLds, bool kLdsCount>
-__global__ __launch_bounds__(256) void k_graph_fill(FrState fs) {
-    extern __shared__ uint64_t sgt[];
-    __shared__ int64_t red[4];
-    const FrCtl *ctl = fs.ctl;
-    if (ctl->done) return;
-    const int s = ctl->s, N = fs.N;
-    const uint64_t *tr = fs.gtree;
-    int *cnt = fs.count;
-    if (kLds) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) sgt[i] = fs.gtree[i];
-        __syncthreads();
-        for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
-            uint32_t b = fs.full[w];
-            while (b) {
-                const int i = w * 32 + __ffs(b) - 1;
-                b &= b - 1;
-                if (i != s) sgt[i] |= kGFilled;
-            }
-        }
-        tr = sgt;
-    }
-    if (kLdsCount) {
-        cnt = (int *)(sgt + (kLds ? N : 0));
-        for (int i = threadIdx.x; i < N; i += blockDim.x) cnt[i] = 0;
-    }
-    __syncthreads();
-    int64_t mine = 0;
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
-        if (v == s) continue;
-        if (kLds ? (tr[v] & kGFilled) != 0 : ((fs.full[v >> 5] >> (v & 31)) & 1u) != 0) continue;
-        const int n = graph_fill_from<kLds, kLdsCount>(fs, tr, v, s, cnt);
-        if (n) count_add(fs, v, n);
-        mine += n;
-    }
-    if (kLdsCount) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < N; i += blockDim.x)
-            if (cnt[i]) count_add(fs, i, cnt[i]);
-    }
-    const int64_t tot = block_sum_i64(mine, red);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&fs.ctl->filled, (unsigned long long)tot);
-    if (blockIdx.x == 0) {
-        uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
-        for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
-            const int lo = w * 32;
-            mrow[w] = (N - lo >= 32) ? 0xFFFFFFFFu : ((1u << (N - lo)) - 1u);
-        }
-        if (threadIdx.x == 0) {
-            fs.count[s] = N;
-            atomicOr(&fs.full[s >> 5], 1u << (s & 31));
-        }
-    }
-}
-
 }  // namespace
-
-// ---- layouts (host) ---------------------------------------------------------------------------
-size_t weight_block_bytes(int H, int W) {
-    const size_t n = (size_t)H * W;
-    return 7 * al256(n * 2) + 2 * al256(n * 4);
-}
-
-GImgW weight_block_layout(void *dev, int H, int W, int conn) {
-    char *p = (char *)dev;
-    const size_t n = (size_t)H * W;
-    GImgW w;
-    w.H = H; w.W = W; w.N = H * W; w.conn = conn;
-    uint16_t **u16[7] = {&w.wr, &w.wd, &w.wdr, &w.wdl, &w.cwv, &w.cwdr, &w.cwdl};
-    for (auto **q : u16) { *q = (uint16_t *)p; p += al256(n * 2); }
-    w.P = (int32_t *)p; p += al256(n * 4);
-    w.cP = (int32_t *)p;
-    return w;
-}
-
-size_t fr_workspace_bytes(int N, bool spec) {
-    const size_t MW = ((size_t)N + 31) / 32;
-    size_t b = al256((size_t)N * MW * 4) + 7 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
-    if (spec)
-        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + 2 * al256(kSpecSlots * 4) +
-             al256(2 * kSpecK * 4);
-    return b;
-}
-
-FrState fr_workspace_layout(void *ws, int N, bool spec) {
-    char *p = (char *)ws;
-    FrState f{};
-    f.N = N;
-    f.MW = (N + 31) / 32;
-    f.mask = (uint32_t *)p; p += al256((size_t)N * f.MW * 4);
-    f.count = (int32_t *)p; p += al256((size_t)N * 4);
-    f.rank = (int32_t *)p; p += al256((size_t)N * 4);
-    f.order = (int32_t *)p; p += al256((size_t)N * 4);
-    f.packed = (uint32_t *)p; p += al256((size_t)N * 4);
-    f.dbuf = (int32_t *)p; p += al256((size_t)N * 4);
-    f.full = (uint32_t *)p; p += al256((size_t)N * 4);
-    f.sp_in = (int32_t *)p; p += al256((size_t)N * 4);  // a spiral turn has at most N pixels
-    f.ctl = (FrCtl *)p; p += al256(sizeof(FrCtl));
-    if (spec) {
-        f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * N * 4);
-        f.src_slot = (int32_t *)p; p += al256((size_t)N * 4);
-        f.slot_src = (int32_t *)p; p += al256(kSpecSlots * 4);
-        f.slot_state = (int32_t *)p; p += al256(kSpecSlots * 4);
-        f.spec_list = (int32_t *)p;
-    }
-    return f;
-}
-
-// ---- launchers ----------------------------------------------------------------------------------
-hipError_t launch_prep(const GImgW &w, const uint8_t *img_dev, int C, int wmode, hipStream_t st) {
-    const int blocks = (w.N + 255) / 256;
-    hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, w, img_dev, C, wmode);
-    hipLaunchKernelGGL(k_prefix, dim3((w.H + w.W + 63) / 64), dim3(64), 0, st, w);
-    return hipGetLastError();
-}
-
-hipError_t launch_prep_batched(const GImgW *w_dev, const uint8_t *imgs_dev, const int64_t *img_off_dev, int B,
-                               int C, int wmode, hipStream_t st) {
-    hipLaunchKernelGGL(k_prep_batched, dim3(64, B), dim3(256), 0, st, w_dev, imgs_dev, img_off_dev, C, wmode);
-    hipLaunchKernelGGL(k_prefix_batched, dim3(B), dim3(256), 0, st, w_dev);
-    return hipGetLastError();
-}
-
-hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st) {
-    if (K <= 0) return hipSuccess;
-    return dispatch<RelaxRows>(g.conn, g.H > g.W ? g.H : g.W, g, src_list, src_base, K, out, max_rounds, ctl,
-                               st);
-}
-
-hipError_t launch_fr_init(const FrState &fs, hipStream_t st) {
-    hipLaunchKernelGGL(k_fr_init, dim3((fs.N + 255) / 256), dim3(256), 0, st, fs);
-    return hipGetLastError();
-}
-
-hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
-    return dispatch<FrSetup>(g.conn, g.H > g.W ? g.H : g.W, g, fs, max_rounds, st);
-}
-
-hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
-    return dispatch<FrStep>(g.conn, g.H > g.W ? g.H : g.W, g, fs, max_rounds, st, mid);
-}
-
-hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line, size_t lds_bytes,
-                                     int conn, int32_t *out, int max_rounds, FrCtl *ctl, hipStream_t st) {
-    if (n_items <= 0) return hipSuccess;
-    return dispatch<RelaxRowsBatched>(conn, max_line, imgs_dev, B, n_items, lds_bytes, out, max_rounds, ctl, st);
-}
-
-hipError_t launch_fr_batched_setup(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, int conn,
-                                   int max_rounds, hipStream_t st) {
-    if (B <= 0) return hipSuccess;
-    return dispatch<FrBatchedSetup>(conn, max_line, imgs_dev, B, maxN, lds, max_rounds, st);
-}
-
-hipError_t launch_fr_batched_step(const BImg *imgs_dev, int B, int max_line, int maxN, size_t lds, size_t wbytes,
-                                  int conn, int max_rounds, int *batch_done, hipStream_t st) {
-    if (B <= 0) return hipSuccess;
-    return dispatch<FrBatchedStep>(conn, max_line, imgs_dev, B, maxN, lds, wbytes, max_rounds, batch_done, st);
-}
-
-size_t graph_workspace_bytes(int n) { return fr_workspace_bytes(n, false) + al256((size_t)n * 8); }
-
-FrState graph_workspace_layout(void *ws, int n) {
-    FrState f = fr_workspace_layout(ws, n, false);
-    f.gtree = (uint64_t *)((char *)ws + fr_workspace_bytes(n, false));
-    return f;
-}
-
-
-hipError_t launch_graph_rows(const GGraph &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st) {
-    if (K <= 0) return hipSuccess;
-    const size_t lds = graph_prop_lds(g.n);
-    hipError_t e = set_lds(k_graph_rows, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_graph_rows, dim3(K), dim3(kRelaxThreads), lds, st, g, src_list, src_base, out, max_rounds,
-                       ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_graph_setup(const GGraph &g, const FrState &fs, int max_rounds, hipStream_t st) {
-    const size_t lds = graph_prop_lds(g.n);
-    hipError_t e = set_lds(k_graph_setup, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_graph_setup, dim3(1), dim3(kRelaxThreads), lds, st, g, fs, max_rounds);
-    hipLaunchKernelGGL(k_rank, dim3((g.n + 255) / 256), dim3(256), 0, st, fs.dbuf, g.n, fs.rank, fs.order);
-    return hipGetLastError();
-}
-
-template <bool kLds, bool kLdsCount>
-static hipError_t launch_graph_fill(const FrState &fs, size_t lds, hipStream_t st) {
-    auto k = k_graph_fill<kLds, kLdsCount>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((fs.N + 255) / 256), dim3(256), lds, st, fs);
-    return hipGetLastError();
-}
-
-hipError_t launch_graph_step(const GGraph &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
-    const size_t lds = graph_prop_lds(g.n);
-    hipError_t e = set_lds(k_graph_step, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_graph_step, dim3(1), dim3(kRelaxThreads), lds, st, g, fs, max_rounds);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (mid) {
-        e = hipEventRecord(mid, st);
-        if (e != hipSuccess) return e;
-    }
-    const size_t tb = (size_t)g.n * 8, cb = (size_t)g.n * 4;
-    if (tb + cb <= kMaxLds) return launch_graph_fill<true, true>(fs, tb + cb, st);
-    if (tb <= kMaxLds) return launch_graph_fill<true, false>(fs, tb, st);
-    return launch_graph_fill<false, false>(fs, 0, st);
-}
 
 }  // namespace gapd

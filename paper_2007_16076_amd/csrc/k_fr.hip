@@ -1,0 +1,179 @@
+// The tree-based methods on one image: setup (geodesic centroid and extrema
+// ranks, Section 3.3), loop steps (selection + propagation + tree, Sections
+// 3.1-3.4) and the redundancy fill beside the speculative propagations.
+#include "dev_common.h"
+
+namespace gapd {
+
+namespace {
+
+template <int CONN, int S>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_setup(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    fr_setup_block<CONN, S>(g, Wp, fs, smem, max_rounds, red);
+}
+
+template <int CONN, int S, bool kStageW>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_step(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    fr_step_block<CONN, S, kStageW>(g, Wp, fs, max_rounds, smem, red, nullptr);
+}
+
+// Static LDS of the speculation plan's sort keys (beyond the usual reserve).
+constexpr size_t kSpecSortLds = (2 * kRelaxThreads + kSpecSlots) * sizeof(uint64_t);
+
+template <int CONN, int S, bool kStageW>
+__global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ uint64_t red[kRelaxThreads / 64];
+    __shared__ uint64_t keys[2 * kRelaxThreads];
+    __shared__ uint64_t skeys[kSpecSlots];
+    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys);
+}
+
+template <bool kLds, bool kLdsCount>
+__global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
+    extern __shared__ uint32_t spk[];
+    __shared__ int64_t red[4];
+    fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
+}
+
+// The fill of the current step (blocks kSpecK..) beside the speculative
+// propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
+// that the longer propagations start at once).  With the grandparent table
+// only 128 threads of a fill block walk (all 256 stage the tables): the
+// walks then spread over twice the compute units, which pays for the extra
+// staging.
+template <int CONN, int S, bool kStageW, bool kLdsCount, bool kA2 = false>
+__global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
+    extern __shared__ int smem[];
+    __shared__ int64_t red[4];
+    if (fs.ctl->done) return;
+    if ((int)blockIdx.x < kSpecK) {
+        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, smem, blockIdx.x);
+        return;
+    }
+    const int slot = fs.ctl->tree_slot;
+    const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
+    fr_fill_block<true, kLdsCount, kA2, kA2 ? 128 : 256>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
+                                                         gridDim.x - kSpecK);
+}
+
+template <int CONN, int S>
+struct FrSetup {
+    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
+        const int Wp = lds_row_stride(g.W);
+        const size_t lds = (size_t)g.H * Wp * sizeof(int);
+        auto k1 = k_fr_setup<CONN, S>;
+        hipError_t e = set_lds(k1, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        hipLaunchKernelGGL(k_rank, dim3((g.N + 255) / 256), dim3(256), 0, st, fs.dbuf, g.N, fs.rank, fs.order);
+        return hipGetLastError();
+    }
+};
+
+template <int CONN, int S>
+struct FrStep {
+    template <bool kStageW, bool kLdsCount, bool kA2 = false>
+    static hipError_t launch_fill_spec(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
+                                       size_t lds, int blocks) {
+        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount, kA2>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(kSpecK + blocks), dim3(256), lds, st, g, Wp, fs, max_rounds);
+        return hipGetLastError();
+    }
+
+    template <bool kStageW>
+    static hipError_t launch_step(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
+                                  size_t lds, bool spec) {
+        auto k1 = spec ? k_fr_step_spec<CONN, S, kStageW> : k_fr_step<CONN, S, kStageW>;
+        hipError_t e = set_lds(k1, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k1, dim3(1), dim3(kRelaxThreads), lds, st, g, Wp, fs, max_rounds);
+        return hipGetLastError();
+    }
+
+    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
+        const int Wp = lds_row_stride(g.W);
+        const size_t lds = (size_t)g.H * Wp * sizeof(int);
+        const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
+        const size_t pk = (size_t)g.N * sizeof(uint32_t);
+        // speculation needs the fill to stage a tree in LDS and the select
+        // kernel to hold its sort keys beside the field
+        const bool spec = fs.cache && pk <= kMaxLds && lds + kSpecSortLds <= kMaxLds;
+        const size_t extra = spec ? kSpecSortLds : 0;
+        hipError_t e = lds + wbytes + extra <= kMaxLds
+                           ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes, spec)
+                           : launch_step<false>(g, Wp, fs, max_rounds, st, lds, spec);
+        if (e != hipSuccess) return e;
+        if (mid) {
+            e = hipEventRecord(mid, st);
+            if (e != hipSuccess) return e;
+        }
+        const int blocks = (g.N + 255) / 256;
+        if (spec) {
+            // the fill beside the speculative propagations
+            const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
+            const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
+            if (a2 <= kMaxLds && g.N < 0xFFFF) {
+                const int blocks2 = (g.N + 127) / 128;  // 128 walking threads per block
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
+                else
+                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
+            } else if (2 * pk <= kMaxLds) {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
+                else
+                    e = launch_fill_spec<false, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);
+            } else {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
+                else
+                    e = launch_fill_spec<false, false>(g, Wp, fs, max_rounds, st, std::max(sp, pk), blocks);
+            }
+            if (e != hipSuccess) return e;
+        } else if (2 * pk <= kMaxLds) {
+            auto k2 = k_fr_fill<true, true>;
+            e = set_lds(k2, 2 * pk);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), 2 * pk, st, fs, g.W);
+        } else if (pk <= kMaxLds) {
+            auto k2 = k_fr_fill<true, false>;
+            e = set_lds(k2, pk);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k2, dim3(blocks), dim3(256), pk, st, fs, g.W);
+        } else {
+            hipLaunchKernelGGL((k_fr_fill<false, false>), dim3(blocks), dim3(256), 0, st, fs, g.W);
+        }
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+// ---- launchers ----------------------------------------------------------------------------------
+// This file is compiled once per (connectivity, size class) pair, given by
+// GAPD_CONN and GAPD_S, so the instantiations build in parallel; the
+// dispatch over the pairs is launch_fr_setup / launch_fr_step (k_misc.hip).
+#if !defined(GAPD_CONN) || !defined(GAPD_S)
+#error "k_fr.hip needs -DGAPD_CONN=<4|8> -DGAPD_S=<32|64|128|192>"
+#endif
+#define GAPD_PART_CAT2(a, b, c) a##_##b##_##c
+#define GAPD_PART_CAT(a, b, c) GAPD_PART_CAT2(a, b, c)
+
+hipError_t GAPD_PART_CAT(fr_setup_part, GAPD_CONN, GAPD_S)(const GImg &g, const FrState &fs, int max_rounds,
+                                                           hipStream_t st) {
+    return FrSetup<GAPD_CONN, GAPD_S>::run(g, fs, max_rounds, st);
+}
+
+hipError_t GAPD_PART_CAT(fr_step_part, GAPD_CONN, GAPD_S)(const GImg &g, const FrState &fs, int max_rounds,
+                                                          hipStream_t st, hipEvent_t mid) {
+    return FrStep<GAPD_CONN, GAPD_S>::run(g, fs, max_rounds, st, mid);
+}
+
+}  // namespace gapd

@@ -246,9 +246,8 @@ int gapd_serve_submit(gapd_server *srv, const gapd_job *job, uint64_t *ticket) {
         if (job->mode != GAPD_MODE_NAIVE && job->mode != GAPD_MODE_TREE_FILL_FR &&
             job->mode != GAPD_MODE_TREE_FILL_EXTREMA)
             return GAPD_EINVAL;
-        const size_t lds = (size_t)job->H * lds_row_stride(job->W) * 4;
-        if (job->mode != GAPD_MODE_NAIVE && lds > kMaxLds) {
-            g_create_error = "filling-rate jobs need the distance field to fit in LDS";
+        if (job->mode != GAPD_MODE_NAIVE && !tree_methods_fit(job->H, job->W)) {
+            g_create_error = "tree-method jobs need both image sides <= 192 (distance field in LDS)";
             return GAPD_EINVAL;
         }
     } else {
