@@ -230,11 +230,15 @@ int gapd_batched_workspace_size(const int32_t *H, const int32_t *W, int B, int C
  *   out_offsets:   HOST, B+1 int64 element offsets (nondecreasing, the span
  *                  of image b at least N_b^2 elements);
  *   n_prop_out:    nullable HOST, B int64: loop propagations per image;
+ *   sources_out:   nullable DEVICE int32, sum of N_b elements: tree modes
+ *                  write image b's sources in order from element
+ *                  N_0 + ... + N_(b-1) on (n_prop_out[b] of them);
  *   workspace:     DEVICE, gapd_batched_workspace_size bytes, 256-aligned.
  * Synchronises the stream before returning. */
 int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const int32_t *W, int B, int C,
                            int conn, int weight_mode, int mode, int32_t *out, const int64_t *out_offsets,
-                           int64_t *n_prop_out, void *workspace, size_t ws_bytes, void *hip_stream);
+                           int64_t *n_prop_out, int32_t *sources_out, void *workspace, size_t ws_bytes,
+                           void *hip_stream);
 
 /* ---- serving ---------------------------------------------------------------------------------- */
 

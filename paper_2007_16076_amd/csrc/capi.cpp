@@ -449,7 +449,7 @@ int gapd_batched_workspace_size(const int32_t *H, const int32_t *W, int B, int C
 
 int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const int32_t *W, int B, int C, int conn,
                            int weight_mode, int mode, int32_t *out, const int64_t *out_offsets, int64_t *n_prop_out,
-                           void *workspace, size_t ws_bytes, void *hip_stream) {
+                           int32_t *sources_out, void *workspace, size_t ws_bytes, void *hip_stream) {
     if (B < 0 || !H || !W || !out_offsets) return GAPD_EINVAL;
     if (B == 0) return GAPD_OK;
     if (!images_packed || !out || !workspace) return GAPD_EINVAL;
@@ -490,6 +490,8 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
     std::vector<GImgW> gw(B);
     std::vector<BImg> bi(B);
     std::vector<int64_t> ioff(B);
+    std::vector<int64_t> seq_off(B + 1, 0);
+    for (int b = 0; b < B; ++b) seq_off[b + 1] = seq_off[b] + (int64_t)H[b] * W[b];
     int64_t items = 0;
     int max_line = 1, maxN = 1;
     size_t lds = 0, wbytes = 0;
@@ -513,6 +515,7 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
             x.fr.W = W[b];
             x.fr.rule = mode == GAPD_MODE_TREE_FILL_EXTREMA ? kRuleExtrema : kRuleFilling;
             x.fr.D = out + out_offsets[b];
+            x.fr.seq_out = sources_out ? sources_out + seq_off[b] : nullptr;
             wbytes = std::max(wbytes, (size_t)(conn == 8 ? 4 : 2) * ((N + 1) / 2) * 4);
         }
         lds = std::max(lds, l);

@@ -84,7 +84,7 @@ def load_library(path: str = LIB_PATH):
         "gapd_strerror": ([I], ctypes.c_char_p),
         "gapd_last_error": ([P], ctypes.c_char_p),
         "gapd_batched_workspace_size": ([P, P, I, I, I, I, ctypes.POINTER(SZ)], I),
-        "gapd_all_pairs_batched": ([P, P, P, I, I, I, I, I, P, P, P, P, SZ, P], I),
+        "gapd_all_pairs_batched": ([P, P, P, I, I, I, I, I, P, P, P, P, P, SZ, P], I),
         "gapd_server_create": ([P, SZ, I, ctypes.POINTER(P)], I),
         "gapd_serve_submit": ([P, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)], I),
         "gapd_serve_poll": ([P, ctypes.c_uint64, ctypes.POINTER(Result)], I),
@@ -266,8 +266,10 @@ def pack_offsets(shapes):
 
 
 def all_pairs_batched(images, mode: int = MODE_NAIVE, conn: int = CONN4, weight_mode: int | None = None,
-                      out=None, offsets=None, workspace=None, stream=None):
-    """All-pairs arrays of many images in one call.  Returns (out, offsets, n_prop)."""
+                      out=None, offsets=None, workspace=None, stream=None, sources_out=None):
+    """All-pairs arrays of many images in one call.  Returns (out, offsets, n_prop).
+    sources_out (tree modes, optional): a device int32 tensor of sum(N_b)
+    elements that receives image b's source sequence from sum(N_0..N_b-1) on."""
     import torch
     imgs = [_img_arr(im) for im in images]
     C = imgs[0][3]
@@ -290,6 +292,7 @@ def all_pairs_batched(images, mode: int = MODE_NAIVE, conn: int = CONN4, weight_
     nprop = np.zeros(B, dtype=np.int64)
     _check(load_library().gapd_all_pairs_batched(packed.ctypes.data, H.ctypes.data, W.ctypes.data, B, C, conn, wmode,
                                                  mode, _dptr(out), offsets.ctypes.data, nprop.ctypes.data,
+                                                 _dptr(sources_out) if sources_out is not None else None,
                                                  _dptr(workspace), workspace.numel(), _stream_ptr(stream)))
     return out, offsets, nprop
 

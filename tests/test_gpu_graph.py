@@ -56,7 +56,8 @@ def run_tree(G, torch, graph, mode, boundary=None):
     n = g.n
     seq = torch.full((n,), -1, dtype=torch.int32, device="cuda")
     fil = torch.zeros((n,), dtype=torch.int64, device="cuda")
-    D, st = g.all_pairs(mode, sources_out=seq, filled_out=fil)
+    D, st = g.all_pairs(mode, out=torch.full((n, n), -7, dtype=torch.int32, device="cuda"), sources_out=seq,
+                        filled_out=fil)
     torch.cuda.synchronize()
     k = st.n_prop
     return D.cpu().numpy(), seq.cpu().numpy()[:k], fil.cpu().numpy()[:k], st
@@ -67,7 +68,7 @@ def test_graph_naive_matches_oracle(G, torch_mod, oracle_lib, n, seed):
     graph = geo(n, seed)
     say("graph naive", n)
     g = G.Graph(*graph)
-    D, st = g.all_pairs(G.MODE_NAIVE)
+    D, st = g.all_pairs(G.MODE_NAIVE, out=torch_mod.full((g.n, g.n), -7, dtype=torch_mod.int32, device="cuda"))
     assert np.array_equal(D.cpu().numpy(), oracle_lib.graph_naive(*graph))
     assert st.n_prop == n
 
@@ -174,12 +175,12 @@ def test_graph_large_fill_paths(G, torch_mod, oracle_lib, n):
     graph = two_level_graph(n, 7)
     say("graph large", n)
     g = G.Graph(*graph)
-    Dn, _ = g.all_pairs(G.MODE_NAIVE)
+    Dn, _ = g.all_pairs(G.MODE_NAIVE, out=torch_mod.full((n, n), -7, dtype=torch_mod.int32, device="cuda"))
     rows = np.array([0, 1, n // 3, n // 2, n - 1], np.int32)
     assert np.array_equal(Dn[torch_mod.from_numpy(rows).long().cuda()].cpu().numpy(),
                           oracle_lib.graph_rows(*graph, rows))
     fil = torch_mod.zeros((n,), dtype=torch_mod.int64, device="cuda")
-    Df, st = g.all_pairs(G.MODE_TREE_FILL_FR, filled_out=fil)
+    Df, st = g.all_pairs(G.MODE_TREE_FILL_FR, out=torch_mod.full((n, n), -7, dtype=torch_mod.int32, device="cuda"), filled_out=fil)
     assert torch_mod.equal(Df, Dn)
     assert int(fil[st.n_prop - 1]) == n * (n - 1) // 2
     del Df, Dn

@@ -52,9 +52,11 @@ def run_method(G, torch, img, conn, mode=None, draws=None, h=0):
     seq = torch.full((N,), -1, dtype=torch.int32, device="cuda")
     fil = torch.zeros((N,), dtype=torch.int64, device="cuda")
     if draws is None:
-        D, st = ctx.all_pairs(mode, sources_out=seq, filled_out=fil)
+        D, st = ctx.all_pairs(mode, out=torch.full((N, N), -7, dtype=torch.int32, device="cuda"),
+                              sources_out=seq, filled_out=fil)
     else:
-        D, st = ctx.all_pairs_spiral(draws, h=h, sources_out=seq, filled_out=fil)
+        D, st = ctx.all_pairs_spiral(draws, h=h, out=torch.full((N, N), -7, dtype=torch.int32, device="cuda"),
+                                     sources_out=seq, filled_out=fil)
     torch.cuda.synchronize()
     k = st.n_prop
     return D.cpu().numpy(), seq.cpu().numpy()[:k], fil.cpu().numpy()[:k], st

@@ -37,6 +37,11 @@ def G(torch_mod):
     return gapd
 
 
+def poisoned(torch, *shape):
+    """An int32 output pre-filled with -7, so a skipped write cannot pass as an old result."""
+    return torch.full(shape, -7, dtype=torch.int32, device="cuda")
+
+
 def rand_img(seed, h, w, c=1, lo=1, hi=255):
     rng = np.random.default_rng(seed)
     shape = (h, w) if c == 1 else (h, w, c)
@@ -48,7 +53,7 @@ def run_fr(G, torch, img, conn):
     N = ctx.N
     seq = torch.full((N,), -1, dtype=torch.int32, device="cuda")
     fil = torch.zeros((N,), dtype=torch.int64, device="cuda")
-    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, sources_out=seq, filled_out=fil)
+    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, out=poisoned(torch, N, N), sources_out=seq, filled_out=fil)
     torch.cuda.synchronize()
     k = st.n_prop
     return D.cpu().numpy(), seq.cpu().numpy()[:k], fil.cpu().numpy()[:k], st
@@ -65,7 +70,7 @@ SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (5, 9), (32, 32), (33, 65), (70, 3), (
 def test_naive_matches_oracle(G, torch_mod, oracle_lib, shape, conn):
     say("naive", shape, conn)
     img = rand_img(sum(shape) + conn, *shape)
-    D, st = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE)
+    D, st = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE, out=poisoned(torch_mod, img.size, img.size))
     ref = oracle_lib.naive(img, conn=conn)
     assert np.array_equal(D.cpu().numpy(), ref)
     assert st.n_prop == img.size
@@ -76,7 +81,8 @@ def test_naive_matches_oracle(G, torch_mod, oracle_lib, shape, conn):
 def test_naive_multiband_matches_oracle(G, torch_mod, oracle_lib, conn, bands):
     say("naive multiband", bands, conn)
     img = rand_img(bands * 10 + conn, 21, 27, c=bands, lo=0)
-    D, _ = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE)
+    N = img.shape[0] * img.shape[1]
+    D, _ = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE, out=poisoned(torch_mod, N, N))
     assert np.array_equal(D.cpu().numpy(), oracle_lib.naive(img, conn=conn))
 
 
@@ -84,7 +90,7 @@ def test_naive_constant_and_plateau_images(G, torch_mod, oracle_lib):
     say("ties")
     for img in (np.full((9, 14), 3, np.uint8), np.kron(rand_img(4, 4, 5), np.ones((5, 5), np.uint8))):
         for conn in (4, 8):
-            D, _ = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE)
+            D, _ = G.Context(img, conn=conn).all_pairs(G.MODE_NAIVE, out=poisoned(torch_mod, img.size, img.size))
             assert np.array_equal(D.cpu().numpy(), oracle_lib.naive(img, conn=conn))
 
 
@@ -135,7 +141,7 @@ def test_filling_rate_blob_128_sampled(G, torch_mod, oracle_lib):
     ctx = G.Context(img)
     torch = torch_mod
     seq = torch.full((ctx.N,), -1, dtype=torch.int32, device="cuda")
-    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, sources_out=seq)
+    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, out=poisoned(torch, ctx.N, ctx.N), sources_out=seq)
     torch.cuda.synchronize()
     say("fr blob128 done", st.n_prop, st.ms_total)
     rng = np.random.default_rng(7)
@@ -162,7 +168,7 @@ def test_filling_rate_voronoi_192_sampled(G, torch_mod, oracle_lib):
     torch = torch_mod
     N = ctx.N
     fil = torch.zeros((N,), dtype=torch.int64, device="cuda")
-    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, filled_out=fil)
+    D, st = ctx.all_pairs(G.MODE_TREE_FILL_FR, out=poisoned(torch, N, N), filled_out=fil)
     torch.cuda.synchronize()
     say("fr voronoi192 done", st.n_prop, st.ms_total, st.n_cache_hits)
     assert int(fil[st.n_prop - 1]) == N * (N - 1) // 2
@@ -170,7 +176,7 @@ def test_filling_rate_voronoi_192_sampled(G, torch_mod, oracle_lib):
     rows = np.random.default_rng(8).choice(N, size=8, replace=False)
     ref = oracle_lib.rows(img, rows)
     assert np.array_equal(D[torch.as_tensor(rows, device="cuda")].cpu().numpy(), ref)
-    Dn, _ = ctx.all_pairs(G.MODE_NAIVE)
+    Dn, _ = ctx.all_pairs(G.MODE_NAIVE, out=poisoned(torch, N, N))
     assert torch.equal(D, Dn)
     del D, Dn
     torch.cuda.empty_cache()
@@ -183,7 +189,7 @@ def test_sssp_matches_oracle(G, torch_mod, oracle_lib):
     img = rand_img(3, 40, 50)
     ctx = G.Context(img)
     src = np.array([0, 1999, 777, 1000, 1000], dtype=np.int32)
-    out = ctx.sssp(src).cpu().numpy()
+    out = ctx.sssp(src, out=poisoned(torch_mod, src.size, ctx.N)).cpu().numpy()
     assert np.array_equal(out, oracle_lib.rows(img, src))
 
 
@@ -195,7 +201,7 @@ def test_sssp_large_image_global_field(G, torch_mod, oracle_lib):
     img = synth.blob_image(np.random.default_rng(12), 512, 512)
     ctx = G.Context(img)
     src = np.array([0, 512 * 512 - 1, 123456, 77], dtype=np.int32)
-    out = ctx.sssp(src).cpu().numpy()
+    out = ctx.sssp(src, out=poisoned(torch_mod, src.size, ctx.N)).cpu().numpy()
     assert np.array_equal(out, oracle_lib.rows(img, src))
 
 
@@ -214,7 +220,8 @@ def test_batched_matches_solo(G, torch_mod, oracle_lib, mode):
     rng = np.random.default_rng(99)
     imgs = [rng.integers(1, 256, size=(int(rng.integers(1, 30)), int(rng.integers(1, 30))), dtype=np.uint8)
             for _ in range(12)]
-    out, offs, nprop = G.all_pairs_batched(imgs, mode=mode)
+    offs = G.pack_offsets([im.shape for im in imgs])
+    out, offs, nprop = G.all_pairs_batched(imgs, mode=mode, out=poisoned(torch_mod, int(offs[-1])), offsets=offs)
     o = out.cpu().numpy()
     for b, im in enumerate(imgs):
         N = im.size

@@ -52,7 +52,8 @@ def test_mix_equals_alone_and_oracle(G, torch_mod, oracle_lib):
     jobs = make_jobs()
     # alone: one slot, one job at a time
     alone = []
-    srv1 = G.Server(1 << 30, max_slots=1)
+    torch = torch_mod
+    srv1 = G.Server(0, max_slots=1, arena=torch.full((1 << 30,), 0xF9, dtype=torch.uint8, device="cuda"))
     for job in jobs:
         t = submit(srv1, G, job)
         r = srv1.wait(t)
@@ -60,7 +61,7 @@ def test_mix_equals_alone_and_oracle(G, torch_mod, oracle_lib):
         srv1.release(t)
     srv1.close()
     # mixed: everything submitted at once to 4 slots
-    srv = G.Server(1 << 30, max_slots=4)
+    srv = G.Server(0, max_slots=4, arena=torch.full((1 << 30,), 0xF9, dtype=torch.uint8, device="cuda"))
     tickets = [submit(srv, G, job) for job in jobs]
     spans = []
     for job, t, ref in zip(jobs, tickets, alone):
