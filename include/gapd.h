@@ -164,6 +164,22 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
  * No setup propagations (st->n_prop_setup = 0, st->centroid = -1). */
 int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *out, gapd_stats *st);
 
+/* gapd_all_pairs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results, with the tree modes' workspace taken from a fixed device
+ * scratch of 64 MiB that the library holds on every device it runs on until
+ * the process ends, instead of the caller's workspace.  It calls no
+ * hipMalloc, hipFree, event creation or other allocating routine (the
+ * first call on a device looks up the scratch's address once).  Tree modes
+ * whose workspace (gapd_workspace_size) exceeds 64 MiB give GAPD_ENOMEM
+ * (N up to about 18000 fit); the naive mode needs no scratch.  Every call on
+ * one device shares that device's scratch, and each call clears what it
+ * needs at its start, so calls that overlap on one device (several streams
+ * or threads) race and must be serialised by the caller.  Timing fields of
+ * st stay 0.  Returns when the result is complete (the call synchronises the
+ * context's stream). */
+int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
+
 /* Release the context and its device memory (not the caller's buffers). */
 void gapd_destroy(gapd_ctx *ctx);
 

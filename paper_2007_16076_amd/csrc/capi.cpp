@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -73,6 +74,7 @@ int max_rounds_for(int N) {
 
 struct gapd_ctx {
     int H = 0, W = 0, C = 0, N = 0, conn = 4, wmode = 0;
+    int device = 0;             // the device current at gapd_create
     hipStream_t stream = nullptr;
     void *dev = nullptr;
     uint8_t *img_dev = nullptr;
@@ -143,6 +145,7 @@ int gapd_create(const uint8_t *image, int H, int W, int C, int conn, int weight_
     gapd_ctx *c = new gapd_ctx();
     c->H = H; c->W = W; c->C = C; c->N = H * W; c->conn = conn; c->wmode = weight_mode;
     c->max_rounds = max_rounds_for(c->N);
+    if (hipGetDevice(&c->device) != hipSuccess) { g_create_error = "no current device"; delete c; return GAPD_EDEVICE; }
     const size_t nimg = al256((size_t)c->N * C);
     const size_t nw = weight_block_bytes(H, W);
     const size_t bytes = nimg + nw + al256(sizeof(FrCtl));
@@ -290,6 +293,97 @@ int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *
     if (!out || !draws) return fail(ctx, GAPD_EINVAL, "out or draws is null");
     if (h < 0 || h > 65536) return fail(ctx, GAPD_EINVAL, "repulsion distance out of range");
     return all_pairs_impl(ctx, kRuleSpiral, h, draws, out, stp);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// A fixed device scratch for callers that cannot allocate device memory.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+// Largest tree-method workspace the fixed scratch holds: 64 MiB covers the
+// filled-pairs matrix and the tree cache up to N of about 18000 pixels (the
+// 128 x 128 workload needs 40.6 MiB).
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+
+// Every device that loads the library holds its own copy of this array until
+// the process ends.  In host code its name is only a host-side stand-in:
+// kernels get the device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device with
+// that device current (the previous current device is restored).
+int scratch_on(int device, void **ptr, std::string &why) {
+    if (device < 0 || device >= kMaxDevices) { why = "device id out of range for the fixed scratch"; return GAPD_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            why = std::string("looking up the fixed scratch: ") + hipGetErrorString(e);
+            return GAPD_EDEVICE;
+        }
+        g_scratch_dev[device] = p;
+    }
+    *ptr = g_scratch_dev[device];
+    return GAPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
+    int st = ctx_check(ctx);
+    if (st) return st;
+    if (!out) return fail(ctx, GAPD_EINVAL, "out is null");
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return fail(ctx, GAPD_EINVAL, "unknown mode (the spiral methods are not offered here)");
+    gapd_stats local{};
+    gapd_stats &s = stp ? *stp : local;
+    s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
+    s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    if (mode == GAPD_MODE_NAIVE) {
+        // no scratch: the naive method only needs the context's control block
+        st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
+                      ctx->poisoned, &s.rounds);
+        if (st == GAPD_OK) s.n_prop = ctx->N;
+        return st;
+    }
+    if (!tree_methods_fit(ctx->H, ctx->W))
+        return fail(ctx, GAPD_EINVAL, "the tree methods need both image sides <= 192 (distance field in LDS)");
+    const size_t need = fr_workspace_bytes(ctx->N, true);
+    if (need > kNoAllocScratchBytes)
+        return fail(ctx, GAPD_ENOMEM, "the tree-method workspace (" + std::to_string(need) +
+                                          " bytes) exceeds the fixed scratch of 64 MiB (N up to about 18000)");
+    void *ws = nullptr;
+    st = scratch_on(ctx->device, &ws, ctx->err);
+    if (st) return st;
+    FrState fs = fr_workspace_layout(ws, ctx->N, true);
+    fs.H = ctx->g.H;
+    fs.W = ctx->g.W;
+    fs.rule = mode == GAPD_MODE_TREE_FILL_FR ? kRuleFilling : kRuleExtrema;
+    fs.D = out;
+    fs.seq_out = s.sources_out;
+    fs.filled_out = s.filled_out;
+    FrCtl hc{};
+    st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, nullptr, hc, ctx->err, ctx->poisoned);
+    s.n_prop = hc.n_prop;
+    s.rounds = hc.rounds;
+    s.n_prop_speculative = hc.spec_props;
+    s.n_cache_hits = hc.spec_hits;
+    s.n_prop_setup = 2;
+    s.centroid = hc.centroid;
+    return st;
 }
 
 void gapd_destroy(gapd_ctx *ctx) {

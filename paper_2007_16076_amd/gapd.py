@@ -24,7 +24,7 @@ JOB_ALL_PAIRS, JOB_MULTI_SOURCE = 0, 1
 
 EXPORTED = [
     "gapd_create", "gapd_set_stream", "gapd_workspace_size", "gapd_set_workspace", "gapd_sssp",
-    "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
+    "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_all_pairs_noalloc", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
     "gapd_all_pairs_batched", "gapd_server_create", "gapd_serve_submit", "gapd_serve_poll", "gapd_serve_wait",
     "gapd_serve_release", "gapd_server_destroy", "gapd_graph_create", "gapd_graph_set_stream",
     "gapd_graph_workspace_size", "gapd_graph_set_workspace", "gapd_graph_sssp", "gapd_graph_all_pairs",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
         "gapd_strerror": ([I], ctypes.c_char_p),
         "gapd_last_error": ([P], ctypes.c_char_p),
         "gapd_batched_workspace_size": ([P, P, I, I, I, I, ctypes.POINTER(SZ)], I),
+        "gapd_all_pairs_noalloc": ([P, I, P, ctypes.POINTER(Stats)], I),
         "gapd_all_pairs_batched": ([P, P, P, I, I, I, I, I, P, P, P, P, P, SZ, P], I),
         "gapd_server_create": ([P, SZ, I, ctypes.POINTER(P)], I),
         "gapd_serve_submit": ([P, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)], I),
@@ -220,6 +221,15 @@ class Context:
         st.filled_out = _dptr(filled_out) if filled_out is not None else None
         st.time_kernels = 1 if time_kernels else 0
         _check(load_library().gapd_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
+        return out, _stats(st)
+
+    def all_pairs_noalloc(self, mode: int, out, sources_out=None, filled_out=None):
+        """gapd_all_pairs_noalloc: the library allocates nothing (the tree modes use
+        its fixed 64 MiB device scratch); out is the caller's (N, N) int32 tensor."""
+        st = Stats()
+        st.sources_out = _dptr(sources_out) if sources_out is not None else None
+        st.filled_out = _dptr(filled_out) if filled_out is not None else None
+        _check(load_library().gapd_all_pairs_noalloc(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
         return out, _stats(st)
 
     def all_pairs_spiral(self, draws, h: int = 0, out=None, sources_out=None, filled_out=None,
