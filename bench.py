@@ -151,9 +151,65 @@ def roofline_hbm(bytes_per_launch, ms):
 
 
 def kernels_sha256():
-    path = os.path.join(ROOT, "paper_2007_16076_amd", "csrc", "kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 over the device-code sources (dev_common.h and the k_*.hip files, in name order)."""
+    csrc = os.path.join(ROOT, "paper_2007_16076_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name == "dev_common.h" or (name.startswith("k_") and name.endswith(".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def wall_clock_khz():
+    """The device's constant clock (hipDeviceAttributeWallClockRate = 10017), in kHz."""
+    import ctypes
+    import torch
+    try:
+        lib = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if lib.hipDeviceGetAttribute(ctypes.byref(v), 10017, torch.cuda.current_device()) == 0 and v.value > 0:
+            return v.value
+    except OSError:
+        pass
+    return 100000
+
+
+def fill_trace(ctx, mode, out, path=None):
+    """One extra call with the per-step trace of the tree modes: what each
+    fill launch walked and found, and how long its blocks took.  Returns a
+    summary by phase of the run; the per-step table goes to ``path``."""
+    import torch
+    N = ctx.N
+    tr = torch.zeros(16 * N, dtype=torch.int64, device="cuda")
+    _, st = ctx.all_pairs(mode, out=out, step_trace=tr)
+    torch.cuda.synchronize()
+    t = tr.view(N, 16)[: st.n_prop].cpu().numpy().astype(np.float64)
+    us = 1e3 / wall_clock_khz()
+    start = (2.0 ** 63 - 1) - t[:, 6]
+    span = np.where(t[:, 11] > 0, (t[:, 7] - start) * us, 0.0)
+    launch_span = np.where(t[:, 8] > 0, (np.maximum(t[:, 7], t[:, 13]) - start) * us, span)
+    cols = {"visits": t[:, 0], "new_pairs": t[:, 1], "max_walk": t[:, 2], "walkers": t[:, 3],
+            "fill_span_us": span, "fill_block_max_us": t[:, 4] * us,
+            "fill_block_mean_us": t[:, 5] * us / np.maximum(t[:, 11], 1), "spec_pieces": t[:, 8],
+            "spec_max_us": t[:, 9] * us, "select_us": t[:, 10] * us, "spec_converged": t[:, 12],
+            "launch_span_us": launch_span,
+            "spec_tail_us": np.where(t[:, 8] > 0, np.maximum(t[:, 13] - t[:, 7], 0.0) * us, 0.0),
+            "cache_hit": t[:, 14]}
+    n = st.n_prop
+    edges = sorted({0, min(100, n), min(1000, n), min(3000, n), min(6000, n), min(9000, n), n})
+    phases = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        if b > a:
+            phases.append(dict(steps=[int(a), int(b)], **{k: round(float(v[a:b].mean()), 2) for k, v in cols.items()}))
+    summary = {"n_prop": int(n), "ms_total": round(st.ms_total, 3),
+               "totals": {"visits": float(t[:, 0].sum()), "new_pairs": float(t[:, 1].sum())},
+               "mean": {k: round(float(v.mean()), 2) for k, v in cols.items()},
+               "max": {k: round(float(v.max()), 2) for k, v in cols.items()}, "phases": phases}
+    if path:
+        np.savetxt(path, np.column_stack([cols[k] for k in cols]), fmt="%.3f", delimiter=",",
+                   header=",".join(cols), comments="")
+    return summary
 
 
 def measured_traffic(workload, kernel_prefix):
@@ -253,6 +309,10 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
                 naive=naive, fr_time_over_naive=round(float(np.mean(fr_ms)) / naive["ms_per_call"], 2),
                 roofline=dominant, roofline_other=other, roofline_naive=roof_naive)
     line["config"]["mode"] = "tree_fill_filling_rate (naive timed beside it)"
+    if getattr(args, "fill_trace", None):
+        import torch
+        out = torch.empty((N, N), dtype=torch.int32, device="cuda")
+        line["fill_trace"] = fill_trace(ctx, gapd.MODE_TREE_FILL_FR, out, args.fill_trace)
     return line, ctx
 
 
@@ -508,6 +568,9 @@ def main():
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--serve-mode", default="naive", choices=["naive", "tree_fill"])
+    ap.add_argument("--fill-trace", default=None, metavar="CSV",
+                    help="single-image workloads: one more filling-rate call with the per-step trace; "
+                         "the summary joins the JSON line, the per-step table goes to CSV")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

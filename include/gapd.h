@@ -100,6 +100,19 @@ typedef struct {
                                     likely next sources (not counted in n_prop)          */
     int64_t  n_cache_hits;  /* filling-rate steps whose propagation was such a tree, taken
                                from the cache instead of being propagated again          */
+    int64_t *step_trace;    /* input: nullable DEVICE buffer of 16*N int64, zeroed by the
+                               call; for the filling-rate and extrema modes with the tree
+                               cache, loop step t fills entries 16t..16t+15 with the
+                               ancestors the fill walked, the new pairs, the longest walk,
+                               the pixels that walked, the slowest fill block, the sum over
+                               fill blocks, 2^63-1 minus the first block start, the last
+                               block end, the speculative pieces run, the slowest piece,
+                               the select kernel, the fill blocks, the pieces that reached
+                               their fixed point, the last piece end, 1 if the step's tree
+                               came from the cache, and 0 (times in ticks of the device's
+                               constant clock,
+                               hipDeviceAttributeWallClockRate kHz).  Tracing adds a
+                               little work to those kernels.                             */
 } gapd_stats;
 
 /* ---- single image ------------------------------------------------------------------------ */

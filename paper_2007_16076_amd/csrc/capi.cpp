@@ -249,6 +249,9 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         fs.D = out;
         fs.seq_out = s.sources_out;
         fs.filled_out = s.filled_out;
+        fs.trace = s.step_trace;
+        if (fs.trace)
+            HIP_OR_FAIL(ctx, hipMemsetAsync(fs.trace, 0, sizeof(int64_t) * kTraceFields * (size_t)ctx->N, ctx->stream));
         FrCtl hc{};
         float kt[2] = {0.f, 0.f};
         st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, e1, hc, ctx->err, ctx->poisoned,
@@ -375,6 +378,9 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     fs.D = out;
     fs.seq_out = s.sources_out;
     fs.filled_out = s.filled_out;
+    fs.trace = s.step_trace;
+    if (fs.trace)
+        HIP_OR_FAIL(ctx, hipMemsetAsync(fs.trace, 0, sizeof(int64_t) * kTraceFields * (size_t)ctx->N, ctx->stream));
     FrCtl hc{};
     st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, nullptr, hc, ctx->err, ctx->poisoned);
     s.n_prop = hc.n_prop;

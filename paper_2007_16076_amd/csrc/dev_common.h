@@ -43,6 +43,12 @@ __host__ __device__ inline uint32_t tw_code(uint32_t w) { return w & 15u; }
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Tree-cache slot sl: its tree words, or while running its partial distance field.
+__device__ __forceinline__ uint32_t *slot_tree(const FrState &fs, int sl) { return fs.cache + (size_t)sl * fs.N; }
+
+// Constant-clock timestamp (100 MHz) for the optional per-step trace.
+__device__ __forceinline__ int64_t trace_clock() { return (int64_t)wall_clock64(); }
+
 // ---------------------------------------------------------------------------------------------
 // Edge weights (Section 2, pseudo-metrics).
 // ---------------------------------------------------------------------------------------------
@@ -171,7 +177,6 @@ __device__ __forceinline__ int2 wave_excl_scans(int p, int q, const RowMasks &m)
 // Inputs of one line of a sweep, prefetched into registers.
 template <int C>
 struct LineIn {
-    int cur[C];  // distances as read before relaxing the line
     int P[C];    // running weight sum along the line
     int wc[C];   // cross edge from the previous line, same element
     int wm[C];   // 8-neighbours: cross edge from element e-1 of the previous line
@@ -187,15 +192,19 @@ struct LineIn {
 // C consecutive elements.  Stores go through an atomic min, so the four
 // sweeps of a round may run concurrently on the same distance field: every
 // stored value is the length of a real path, and values only decrease.
-// Line inputs are loaded PF lines ahead into a register ring; all addresses
-// are clamped into the image, so the loads are unconditional.
-// Returns true if this wave lowered a value it had read.
+// Line weights are loaded PF lines ahead into a register ring (PFW, or 4
+// by default: a lone workgroup per compute unit wants a deeper ring to cover
+// the L2 latency), the field values at most 4 lines ahead, so they are read
+// as late as possible; all addresses are clamped into the image, so the loads
+// are unconditional.  Returns true if this wave lowered a value it had read.
 // ---------------------------------------------------------------------------------------------
-template <int CONN, int C, bool FWD, bool G>
+template <int CONN, int C, bool FWD, bool G, int PFW = 0>
 __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, const uint16_t *__restrict__ wv,
                       const uint16_t *__restrict__ wdr, const uint16_t *__restrict__ wdl,
                       const int32_t *__restrict__ P) {
-    constexpr int PF = C <= 4 ? 4 : 2;
+    constexpr int PF = PFW > 0 ? PFW : (C <= 4 ? 4 : 2);
+    constexpr int PD = PF < 4 ? PF : 4;
+    static_assert(PF % PD == 0, "the weight ring must be a multiple of the field ring");
     const int lane = __lane_id();
     const RowMasks rm(lane >> 4);
     const int e0 = lane * C;
@@ -211,13 +220,19 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
         em[j] = okm[j] ? e - 1 : ec[j];
         ep[j] = okp[j] ? e + 1 : ec[j];
     }
+    auto loadd = [&](int (&cur)[C], int step) {
+        const int l = FWD ? step : NL - 1 - step;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int v = ldd<G>(&d[l * ls + ec[j] * es]);
+            cur[j] = ok[j] ? v : kInf;
+        }
+    };
     auto load = [&](LineIn<C> &in, int step) {
         const int l = FWD ? step : NL - 1 - step;
         const int top = FWD ? (l > 0 ? l - 1 : 0) : l;  // line holding the cross edges into l
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const int v = ldd<G>(&d[l * ls + ec[j] * es]);
-            in.cur[j] = ok[j] ? v : kInf;
             in.P[j] = P[l * L + ec[j]];
             in.wc[j] = wv[top * L + ec[j]];
             if (CONN == 8) {
@@ -230,11 +245,11 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
     };
     int prev[C];
     bool changed = false;
-    auto process = [&](const LineIn<C> &in, int step, bool first) {
+    auto process = [&](const LineIn<C> &in, const int (&cur)[C], int step, bool first) {
         const int l = FWD ? step : NL - 1 - step;
         int a[C], t[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) a[j] = first ? in.cur[j] : min(in.cur[j], prev[j] + in.wc[j]);
+        for (int j = 0; j < C; ++j) a[j] = first ? cur[j] : min(cur[j], prev[j] + in.wc[j]);
         if (CONN == 8 && !first) {
             int left_in = __shfl_up(prev[C - 1], 1);
             int right_in = __shfl_down(prev[0], 1);
@@ -266,32 +281,41 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
         for (int j = 0; j < C; ++j) {
             a[j] = ok[j] ? min(min(t[j], ex.x) + in.P[j], min(u[j], ex.y) - in.P[j]) : kInf;
             if (ok[j]) {
-                if (a[j] < in.cur[j]) changed = true;
+                if (a[j] < cur[j]) changed = true;
                 atomicMin(&d[l * ls + ec[j] * es], a[j]);
             }
             prev[j] = a[j];
         }
     };
-    // Ring of PF prefetched lines: slot (step % PF) holds line `step`.  Line
-    // indices past the end are clamped to the last line, so every load in the
-    // steady-state loop is unconditional and the wait counters stay exact.
+    // Rings of prefetched lines: weight slot (step % PF) and field slot
+    // (step % PD) hold line `step`.  Line indices past the end are clamped to
+    // the last line, so every load in the steady-state loop is unconditional
+    // and the wait counters stay exact.
     LineIn<C> S[PF];
+    int F[PD][C];
 #pragma unroll
     for (int i = 0; i < PF; ++i) load(S[i], min(i, NL - 1));
-    process(S[0], 0, true);
+#pragma unroll
+    for (int i = 0; i < PD; ++i) loadd(F[i], min(i, NL - 1));
+    process(S[0], F[0], 0, true);
     load(S[0], min(PF, NL - 1));
+    loadd(F[0], min(PD, NL - 1));
     int base = 1;
     for (; base + PF <= NL; base += PF) {
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int step = base + k;
-            process(S[(1 + k) % PF], step, false);
+            process(S[(1 + k) % PF], F[(1 + k) % PD], step, false);
             load(S[(1 + k) % PF], min(step + PF, NL - 1));
+            loadd(F[(1 + k) % PD], min(step + PD, NL - 1));
         }
     }
 #pragma unroll
     for (int k = 0; k < PF - 1; ++k)
-        if (base + k < NL) process(S[(1 + k) % PF], base + k, false);
+        if (base + k < NL) {
+            process(S[(1 + k) % PF], F[(1 + k) % PD], base + k, false);
+            loadd(F[(1 + k) % PD], min(base + k + PD, NL - 1));
+        }
     return changed;
 }
 
@@ -407,9 +431,14 @@ __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int 
 //
 // With TREE the edge checks also write the tree words to tree[]; *tree_done
 // tells whether the last check (the one that ended the loop) wrote them.
-template <int CONN, int S, bool G = false, bool TREE = false>
+//
+// PFW is the sweeps' weight prefetch depth (0: the default).  With
+// check_first the edge check also runs after the first round: a field resumed
+// from an earlier round may already be the fixed point.
+template <int CONN, int S, bool G = false, bool TREE = false, int PFW = 0>
 __device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds, const NbW *nw = nullptr,
-                                          uint32_t *tree = nullptr, bool *tree_done = nullptr) {
+                                          uint32_t *tree = nullptr, bool *tree_done = nullptr,
+                                          bool check_first = false) {
     constexpr int C = S >= 64 ? S / 64 : 1;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -417,24 +446,27 @@ __device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int ma
     for (;;) {
         bool ch = false;
         if (wave == 0)
-            ch = sweep<CONN, C, true, G>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
+            ch = sweep<CONN, C, true, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
         else if (wave == 1)
-            ch = sweep<CONN, C, false, G>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
+            ch = sweep<CONN, C, false, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
         else if (wave == 2)
-            ch = sweep<CONN, C, true, G>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
+            ch = sweep<CONN, C, true, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
         else if (wave == 3)
-            ch = sweep<CONN, C, false, G>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
+            ch = sweep<CONN, C, false, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
         ++rounds;
         if (!__syncthreads_or(ch)) break;
-        if (rounds >= max_rounds) return -1;
         // A first round that changed anything is almost never the fixed point
         // (paths with turns need a second one): sweep again before checking.
-        if (rounds == 1) continue;
+        if (rounds == 1 && !check_first) {
+            if (rounds >= max_rounds) return -1;
+            continue;
+        }
         const NbW w = nw ? *nw : nbw_of(g);
         if (!__syncthreads_or(field_check<CONN, G, TREE>(g, w, d, Wp, tree))) {
             if (TREE) *tree_done = true;
             break;
         }
+        if (rounds >= max_rounds) return -1;
     }
     return rounds;
 }
@@ -825,6 +857,14 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int x = base + k * (int)blockDim.x;
+            // The complete-row bitmap, rebuilt from the counts: the link fill
+            // adds to the counts without watching them reach N.  A wave's
+            // lanes hold 64 consecutive points.
+            const uint64_t fb = __ballot(x < fs.N && c[k] >= fs.N);
+            if (__lane_id() == 0 && x < fs.N) {
+                fs.full[x >> 5] = (uint32_t)fb;
+                if (x + 32 < fs.N) fs.full[(x >> 5) + 1] = (uint32_t)(fb >> 32);
+            }
             if (x >= fs.N) continue;
             const uint64_t key = sel_key<RULE>(fs, x, c[k], a[k]);
             best = key < best ? key : best;
@@ -1209,6 +1249,235 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Link fill: the redundancy fill (Property 1) in two phases per pixel v.
+// Each block first turns the step's tree words into two LDS tables: L[x] =
+// parent(x) | (d(x) - d(parent(x))) << 16, the parent and the weight of the
+// tree edge into x (kNoId at the root), and G[x] = grandparent(x).
+//   detect: walk v's ancestors u two at a time (G is the chain: one
+//           dependent LDS read per two ancestors; L gives the one between)
+//           and test each pair (u, v) in row v of the filled-pairs matrix.
+//           The loop issues loads only, so the compiler's wait counts stay
+//           exact and PF pairs of ancestors with their matrix words stay in
+//           flight; new pairs are flagged by ancestor position in LDS.
+//   write:  walk again up to the last new pair (LDS only), keeping
+//           d(s,u) = d(s,v) - (edge weights on the way), and for each new pair
+//           write D(u,v) = D(v,u) = d(s,v) - d(s,u), set both matrix bits and
+//           count it.  Stores and atomics are fire-and-forget.
+// Counts: the block sums the increments of the ancestors in LDS (one byte
+// per pixel: at most kFillLanes per block) and adds them once; row v adds
+// its own.  The complete-row bitmap is rebuilt from the counts by the next
+// select.
+// ---------------------------------------------------------------------------------------------
+struct WalkOut {
+    int nnew;     // new pairs
+    int last;     // position (0-based ancestor index) of the last new pair, -1: none
+    int walked;   // ancestors visited
+};
+
+template <int PF>
+__device__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v, uint32_t *flags) {
+    constexpr int kCap = kFillFlagWords * 32;
+    int cur = v;
+    // the next two ancestors of cur and their words of row v; addresses are
+    // clamped into range so that every load is issued
+    auto gen = [&](int &a, int &b, uint32_t &ma, uint32_t &mb) {
+        const int cc = cur < 0 ? v : cur;
+        const int pa = (int)(L[cc] & 0xFFFFu), pb = (int)G[cc];
+        a = (cur < 0 || pa == (int)kNoId) ? -1 : pa;
+        b = (a < 0 || pb == (int)kNoId) ? -1 : pb;
+        ma = mrow[(a < 0 ? v : a) >> 5];
+        mb = mrow[(b < 0 ? v : b) >> 5];
+        cur = b;
+    };
+    int ra[PF], rb[PF];
+    uint32_t wa[PF], wb[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) gen(ra[k], rb[k], wa[k], wb[k]);
+    WalkOut o{0, -1, 0};
+    uint32_t acc = 0;
+    int pos = 0;
+    // one pass over the ring: test each slot, then refill it
+    auto group = [&]() {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int a = ra[k], b = rb[k];
+            // integer flags (1: the ancestor exists / the pair is new)
+            const uint32_t ea = 1u - ((uint32_t)a >> 31), eb = 1u - ((uint32_t)b >> 31);
+            const uint32_t na = ea & ((~wa[k]) >> (a & 31)), nb = eb & ((~wb[k]) >> (b & 31));
+            const uint32_t fa = na & 1u, fb = nb & 1u;
+            acc |= (fa << (pos & 31)) | (fb << ((pos + 1) & 31));
+            o.nnew += (int)(fa + fb);
+            o.last = (fa | fb) ? pos + (int)fb : o.last;
+            o.walked += (int)(ea + eb);
+            pos += 2;
+            if ((pos & 31) == 0) {
+                if (pos <= kCap) flags[(pos >> 5) - 1] = acc;
+                acc = 0;
+            }
+            gen(ra[k], rb[k], wa[k], wb[k]);
+            // keep the program order: each slot is tested just before it is
+            // refilled, so PF slots of loads stay in flight
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // Four passes per loop iteration: the compiler waits for every load at
+    // the loop head, so the head comes once per 8 PF ancestors.
+    while (ra[0] >= 0) {
+        group();
+        if (ra[0] < 0) break;
+        group();
+        if (ra[0] < 0) break;
+        group();
+        if (ra[0] < 0) break;
+        group();
+    }
+    if ((pos & 31) != 0 && pos < kCap) flags[pos >> 5] = acc;
+    return o;
+}
+
+// Pair (u, v) is new: D(u,v) = D(v,u) = dv - du, both matrix bits, counts
+// (u's in the block's byte counters, never the source's: its row is
+// completed by block 0).
+__device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, int32_t *Drow, uint32_t *cnt8, int v,
+                                           int dv, int u, int du, int s) {
+    const int val = dv - du;
+    Drow[u] = val;
+    fs.D[(size_t)u * fs.N + v] = val;
+    atomicOr(&mrow[u >> 5], 1u << (u & 31));
+    if (u != s) {
+        atomicOr(&fs.mask[(size_t)u * fs.MW + (v >> 5)], 1u << (v & 31));
+        atomicAdd(&cnt8[u >> 2], 1u << ((u & 3) * 8));
+    }
+}
+
+__device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t *G, const uint32_t *flags,
+                           uint32_t *cnt8, int v, int dv, int last, int s) {
+    constexpr int kCap = kFillFlagWords * 32;
+    uint32_t *mrow = fs.mask + (size_t)v * fs.MW;
+    int32_t *Drow = fs.D + (size_t)v * fs.N;
+    int cur = v, dcur = dv;
+    for (int p = 0; p <= last; p += 2) {
+        const uint32_t l = L[cur];
+        const int a = (int)(l & 0xFFFFu), b = (int)G[cur];
+        const int da = dcur - (int)(l >> 16);
+        bool na, nb;
+        if (p < kCap) {
+            const uint32_t fw = flags[p >> 5];
+            na = (fw >> (p & 31)) & 1u;
+            nb = (fw >> ((p + 1) & 31)) & 1u;
+        } else {  // beyond the flags: the matrix still holds the answer for these pairs
+            na = !((mrow[a >> 5] >> (a & 31)) & 1u);
+            nb = b != (int)kNoId && !((mrow[b >> 5] >> (b & 31)) & 1u);
+        }
+        if (na) write_pair(fs, mrow, Drow, cnt8, v, dv, a, da, s);
+        if (b == (int)kNoId) break;
+        const int db = da - (int)(L[a] >> 16);
+        if (nb) write_pair(fs, mrow, Drow, cnt8, v, dv, b, db, s);
+        cur = b;
+        dcur = db;
+    }
+}
+
+// The link fill of one block: pixels chunk * kFillLanes .. + kFillLanes.
+// smem: link_fill_lds(N) bytes: L (N words), then a region that first holds
+// the tree words and then G, the byte counters and the new-pair flags.
+__device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
+                                 int chunk) {
+    const FrCtl *ctl = fs.ctl;
+    const int64_t t0 = fs.trace ? trace_clock() : 0;
+    const int s = ctl->s, N = fs.N;
+    uint32_t *L = smem;
+    uint32_t *T = smem + al4w(N);
+    uint16_t *G = (uint16_t *)T;
+    uint32_t *C8 = T + al4w((N + 1) / 2);
+    uint32_t *FL = C8 + al4w((N + 3) / 4);
+    copy_to_lds(T, tree, N);
+    __syncthreads();
+    // U pixels per thread at a time, so that their dependent LDS reads overlap
+    constexpr int U = 8;
+    const int nb = (int)blockDim.x;
+    for (int base = threadIdx.x; base < N; base += nb * U) {
+        uint32_t t[U], tp[U];
+        int p[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) t[k] = T[min(base + k * nb, N - 1)];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int x = min(base + k * nb, N - 1);
+            const uint32_t c = tw_code(t[k]);
+            p[k] = c == kRootCode ? -1 : x + code_dy((int)c) * W + code_dx((int)c);
+            tp[k] = T[p[k] < 0 ? x : p[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (base + k * nb < N)
+                L[base + k * nb] = p[k] < 0 ? kNoId : ((uint32_t)p[k] | ((uint32_t)(tw_dist(t[k]) - tw_dist(tp[k])) << 16));
+    }
+    const int v = chunk * kFillLanes + (int)threadIdx.x;
+    const bool walker = threadIdx.x < kFillLanes && v < N && v != s && !((fs.full[v >> 5] >> (v & 31)) & 1u);
+    const int dv = walker ? tw_dist(T[v]) : 0;
+    __syncthreads();  // the tree words are no longer needed: their space takes G, counters and flags
+    for (int base = threadIdx.x; base < N; base += nb * U) {
+        uint32_t p[U], g[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) p[k] = L[min(base + k * nb, N - 1)] & 0xFFFFu;
+#pragma unroll
+        for (int k = 0; k < U; ++k) g[k] = p[k] == kNoId ? kNoId : (L[p[k]] & 0xFFFFu);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (base + k * nb < N) G[base + k * nb] = (uint16_t)g[k];
+    }
+    for (int i = threadIdx.x; i < (N + 3) / 4; i += blockDim.x) C8[i] = 0;
+    __syncthreads();
+    WalkOut o{0, -1, 0};
+    uint32_t *flags = FL + (size_t)threadIdx.x * kFillFlagWords;
+    if (walker) o = walk_detect<16>(L, G, fs.mask + (size_t)v * fs.MW, v, flags);
+    if (o.nnew) {
+        walk_write(fs, L, G, flags, C8, v, dv, o.last, s);
+        atomicAdd(&fs.count[v], o.nnew);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (N + 3) / 4; i += blockDim.x) {
+        const uint32_t c = C8[i];
+        if (c) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((c >> (8 * j)) & 255u) atomicAdd(&fs.count[4 * i + j], (int)((c >> (8 * j)) & 255u));
+        }
+    }
+    const int64_t tot = block_sum_i64(o.nnew, red);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&fs.ctl->filled, (unsigned long long)tot);
+    if (chunk == 0) {
+        uint32_t *mrow = fs.mask + (size_t)s * fs.MW;
+        for (int w = threadIdx.x; w < fs.MW; w += blockDim.x) {
+            const int lo = w * 32;
+            mrow[w] = (N - lo >= 32) ? 0xFFFFFFFFu : ((1u << (N - lo)) - 1u);
+        }
+        if (threadIdx.x == 0) fs.count[s] = N;
+    }
+    if (fs.trace) {
+        int64_t *tr = fs.trace + (ctl->n_prop - 1) * kTraceFields;
+        const int64_t walked = block_sum_i64(o.walked, red);
+        const int64_t walkers = block_sum_i64(walker ? 1 : 0, red);
+        int mw = o.walked;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mw = max(mw, __shfl_xor(mw, off));
+        if (__lane_id() == 0) atomicMax((unsigned long long *)&tr[kTrMaxWalk], (unsigned long long)mw);
+        if (threadIdx.x == 0) {
+            const int64_t t1 = trace_clock();
+            atomicAdd((unsigned long long *)&tr[kTrVisits], (unsigned long long)walked);
+            atomicAdd((unsigned long long *)&tr[kTrNew], (unsigned long long)tot);
+            atomicAdd((unsigned long long *)&tr[kTrWalkers], (unsigned long long)walkers);
+            atomicMax((unsigned long long *)&tr[kTrBlockMax], (unsigned long long)(t1 - t0));
+            atomicAdd((unsigned long long *)&tr[kTrBlockSum], (unsigned long long)(t1 - t0));
+            atomicMax((unsigned long long *)&tr[kTrStartInv], (unsigned long long)(INT64_MAX - t0));
+            atomicMax((unsigned long long *)&tr[kTrEnd], (unsigned long long)t1);
+            atomicAdd((unsigned long long *)&tr[kTrFillBlocks], 1ull);
+        }
+    }
+}
+
 // Piece j of the speculation plan, one round of a propagation into its
 // cache slot: a new candidate starts in its victim slot (source at 0, the
 // rest infinite), a running one resumes from the partial distance field kept
@@ -1217,13 +1486,15 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
 // ready.  Otherwise the field goes back to the slot.  Any state of the field
 // is a set of real path lengths, so resuming converges to the same
 // distances.  One round stays shorter than the fill it runs beside, so the
-// speculation never lengthens a step.  One block.
+// speculation never lengthens a step.  One block.  Returns 1 when the piece
+// reached the fixed point, -1 when the field goes back to the slot, -3 when
+// the plan has no piece j.
 template <int CONN, int S, bool kStageW>
-__device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
+__device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
     FrCtl *ctl = fs.ctl;
-    if (j >= ctl->spec_n) return;
+    if (j >= ctl->spec_n) return -3;
     const int c = fs.spec_list[j], sl = fs.spec_list[kSpecK + j];
-    uint32_t *tree = fs.cache + (size_t)sl * fs.N;
+    uint32_t *tree = slot_tree(fs, sl);
     int *d = smem;
     NbW w = nbw_of(g);
     if (kStageW) {
@@ -1260,7 +1531,10 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
     }
     __syncthreads();
     bool tree_done = false;
-    const int r = relax_block<CONN, S, false, true>(g, d, Wp, 1, &w, tree, &tree_done);
+    // One sweep round.  A new propagation never converges in its first round;
+    // a resumed field is checked right after it, which saves the round that
+    // would otherwise only confirm the fixed point.
+    const int r = relax_block<CONN, S, false, true>(g, d, Wp, 1, &w, tree, &tree_done, c < 0);
     if (r >= 0) {
         if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, tree);
         __threadfence();
@@ -1277,6 +1551,7 @@ __device__ void fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *sme
         }
     }
     if (threadIdx.x == 0) atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
+    return r;
 }
 
 // ---------------------------------------------------------------------------------------------

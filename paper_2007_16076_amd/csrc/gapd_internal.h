@@ -104,7 +104,44 @@ struct FrState {
     FrCtl *ctl;
     int32_t *seq_out;          // nullable, N
     int64_t *filled_out;       // nullable, N
+    int64_t *trace;            // nullable, kTraceFields per loop step (see gapd_stats.step_trace)
 };
+
+// Per-step trace fields (int64) of the filling-rate loop.
+constexpr int kTraceFields = 16;
+enum TraceField {
+    kTrVisits = 0,     // ancestors walked by the fill (pairs tested)
+    kTrNew = 1,        // new pairs
+    kTrMaxWalk = 2,    // longest walk (ancestors)
+    kTrWalkers = 3,    // pixels that walked (incomplete rows)
+    kTrBlockMax = 4,   // slowest fill block (constant-clock ticks)
+    kTrBlockSum = 5,   // fill-block ticks summed over blocks
+    kTrStartInv = 6,   // max over fill blocks of (2^63 - 1 - start tick)
+    kTrEnd = 7,        // max over fill blocks of the end tick
+    kTrSpecPieces = 8, // speculative pieces run beside the fill
+    kTrSpecMax = 9,    // slowest speculative piece (ticks)
+    kTrSelect = 10,    // select (+ propagation on a miss) kernel (ticks)
+    kTrFillBlocks = 11,  // fill blocks that ran
+    kTrSpecDone = 12,    // speculative pieces that reached their fixed point
+    kTrSpecEnd = 13,     // max over speculative pieces of the end tick
+    kTrHit = 14          // 1: the step's tree came from the cache
+};
+
+// The link fill (the redundancy fill with 16-bit pixel ids in LDS tables).
+constexpr uint32_t kNoId = 0xFFFFu;   // no such pixel (the root's parent)
+__host__ __device__ inline size_t al4w(size_t n) { return (n + 3) & ~size_t(3); }
+// Walking threads per block of the link fill, and 32-bit words of new-pair
+// flags each keeps in LDS (one flag per ancestor; longer walks fall back to
+// re-reading the filled-pairs matrix).
+constexpr int kFillLanes = 128;
+constexpr int kFillFlagWords = 12;
+// LDS of a link-fill block: L (N words), then a region that holds the tree
+// words (N words) and afterwards G (N uint16), the byte counters (N bytes)
+// and the flags.
+__host__ __device__ inline size_t link_fill_lds(int N) {
+    const size_t later = al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + 3) / 4) + (size_t)kFillLanes * kFillFlagWords;
+    return 4 * (al4w(N) + (al4w(N) > later ? al4w(N) : later));
+}
 
 // Speculation: each step lists the kSpecK least-filled points whose trees are
 // not cached; their propagations run beside the fill, into a cache of
@@ -195,5 +232,9 @@ hipError_t launch_fr_batched_step(const BImg *imgs_dev, int B, int max_line, int
 inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }
 // Largest dynamic LDS a workgroup may use.
 constexpr size_t kMaxLds = 160 * 1024 - 1024;
+// The link fill needs 16-bit pixel ids and its tables in LDS.
+__host__ __device__ inline bool link_fill_fits(int N) {
+    return N >= 1 && N < (int)kNoId && link_fill_lds(N) <= kMaxLds;
+}
 
 }  // namespace gapd

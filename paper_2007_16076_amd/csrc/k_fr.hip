@@ -30,7 +30,14 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, 
     __shared__ uint64_t red[kRelaxThreads / 64];
     __shared__ uint64_t keys[2 * kRelaxThreads];
     __shared__ uint64_t skeys[kSpecSlots];
+    const int64_t t0 = fs.trace ? trace_clock() : 0;
     fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys);
+    // thread 0 set the step's state; a step that found D complete records nothing
+    if (fs.trace && threadIdx.x == 0 && !fs.ctl->done) {
+        int64_t *tr = fs.trace + (fs.ctl->n_prop - 1) * kTraceFields;
+        tr[kTrSelect] = trace_clock() - t0;
+        tr[kTrHit] = fs.ctl->tree_slot >= 0;
+    }
 }
 
 template <bool kLds, bool kLdsCount>
@@ -40,25 +47,43 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
 }
 
+// Fill variants of the speculative step: the link fill (kFillLinks, when its
+// tables fit LDS), the walk with a grandparent table (kFillA2) or the plain
+// walk with the tree words in LDS (kFillTree).
+constexpr int kFillTree = 0, kFillA2 = 1, kFillLinks = 2;
+
 // The fill of the current step (blocks kSpecK..) beside the speculative
 // propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
-// that the longer propagations start at once).  With the grandparent table
-// only 128 threads of a fill block walk (all 256 stage the tables): the
-// walks then spread over twice the compute units, which pays for the extra
-// staging.
-template <int CONN, int S, bool kStageW, bool kLdsCount, bool kA2 = false>
+// that the longer propagations start at once).  The link fill and the
+// grandparent walk use kFillLanes (128) walking threads per 256-thread block:
+// the walks then spread over twice the compute units, which pays for the
+// extra staging.
+template <int CONN, int S, bool kStageW, bool kLdsCount, int kFill = kFillTree>
 __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs, int max_rounds) {
     extern __shared__ int smem[];
     __shared__ int64_t red[4];
     if (fs.ctl->done) return;
     if ((int)blockIdx.x < kSpecK) {
-        fr_spec_block<CONN, S, kStageW>(g, Wp, fs, smem, blockIdx.x);
+        const int64_t t0 = fs.trace ? trace_clock() : 0;
+        const int r = fr_spec_block<CONN, S, kStageW>(g, Wp, fs, smem, blockIdx.x);
+        if (fs.trace && threadIdx.x == 0 && r != -3) {
+            int64_t *tr = fs.trace + (fs.ctl->n_prop - 1) * kTraceFields;
+            const int64_t t1 = trace_clock();
+            atomicAdd((unsigned long long *)&tr[kTrSpecPieces], 1ull);
+            atomicMax((unsigned long long *)&tr[kTrSpecMax], (unsigned long long)(t1 - t0));
+            if (r >= 0) atomicAdd((unsigned long long *)&tr[kTrSpecDone], 1ull);
+            atomicMax((unsigned long long *)&tr[kTrSpecEnd], (unsigned long long)t1);
+        }
         return;
     }
     const int slot = fs.ctl->tree_slot;
-    const uint32_t *tree = slot >= 0 ? fs.cache + (size_t)slot * fs.N : fs.packed;
-    fr_fill_block<true, kLdsCount, kA2, kA2 ? 128 : 256>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK,
-                                                         gridDim.x - kSpecK);
+    const uint32_t *tree = slot >= 0 ? slot_tree(fs, slot) : fs.packed;
+    if (kFill == kFillLinks) {
+        fill_links_block(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK);
+    } else {
+        fr_fill_block<true, kLdsCount, kFill == kFillA2, kFill == kFillA2 ? 128 : 256>(
+            fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK, gridDim.x - kSpecK);
+    }
 }
 
 template <int CONN, int S>
@@ -77,10 +102,10 @@ struct FrSetup {
 
 template <int CONN, int S>
 struct FrStep {
-    template <bool kStageW, bool kLdsCount, bool kA2 = false>
+    template <bool kStageW, bool kLdsCount, int kFill = kFillTree>
     static hipError_t launch_fill_spec(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
                                        size_t lds, int blocks) {
-        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount, kA2>;
+        auto k = k_fr_fill_spec<CONN, S, kStageW, kLdsCount, kFill>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(kSpecK + blocks), dim3(256), lds, st, g, Wp, fs, max_rounds);
@@ -119,12 +144,19 @@ struct FrStep {
             // the fill beside the speculative propagations
             const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
             const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
-            if (a2 <= kMaxLds && g.N < 0xFFFF) {
-                const int blocks2 = (g.N + 127) / 128;  // 128 walking threads per block
+            const int blocks2 = (g.N + kFillLanes - 1) / kFillLanes;
+            if (link_fill_fits(g.N)) {
+                const size_t ll = link_fill_lds(g.N);
                 if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
+                    e = launch_fill_spec<true, false, kFillLinks>(g, Wp, fs, max_rounds, st, std::max(sp, ll), blocks2);
                 else
-                    e = launch_fill_spec<false, false, true>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
+                    e = launch_fill_spec<false, false, kFillLinks>(g, Wp, fs, max_rounds, st, std::max(sp, ll),
+                                                                   blocks2);
+            } else if (a2 <= kMaxLds && g.N < 0xFFFF) {
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false, kFillA2>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
+                else
+                    e = launch_fill_spec<false, false, kFillA2>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
             } else if (2 * pk <= kMaxLds) {
                 if (lds + wbytes <= kMaxLds)
                     e = launch_fill_spec<true, true>(g, Wp, fs, max_rounds, st, std::max(sp, 2 * pk), blocks);

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_float), ("ms_setup", ctypes.c_float), ("ms_kernel", ctypes.c_float),
                 ("time_kernels", ctypes.c_int32), ("ms_step_kernels", ctypes.c_float),
                 ("ms_fill_kernels", ctypes.c_float), ("_pad2", ctypes.c_int32),
-                ("n_prop_speculative", ctypes.c_int64), ("n_cache_hits", ctypes.c_int64)]
+                ("n_prop_speculative", ctypes.c_int64), ("n_cache_hits", ctypes.c_int64),
+                ("step_trace", ctypes.c_void_p)]
 
 
 class Job(ctypes.Structure):
@@ -210,8 +211,10 @@ class Context:
         return out
 
     def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None,
-                  time_kernels: bool = False):
-        """The N x N distances array (device int32) and the call's statistics."""
+                  time_kernels: bool = False, step_trace=None):
+        """The N x N distances array (device int32) and the call's statistics.
+        step_trace: optional device int64 tensor of 16 * N entries (per-step
+        counters of the tree modes, see gapd_stats.step_trace)."""
         import torch
         if out is None:
             out = torch.empty((self.N, self.N), dtype=torch.int32, device="cuda")
@@ -219,6 +222,7 @@ class Context:
         st = Stats()
         st.sources_out = _dptr(sources_out) if sources_out is not None else None
         st.filled_out = _dptr(filled_out) if filled_out is not None else None
+        st.step_trace = _dptr(step_trace) if step_trace is not None else None
         st.time_kernels = 1 if time_kernels else 0
         _check(load_library().gapd_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
         return out, _stats(st)
