@@ -1339,7 +1339,7 @@ __device__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint3
 // Pair (u, v) is new: D(u,v) = D(v,u) = dv - du, both matrix bits, counts
 // (u's in the block's byte counters, never the source's: its row is
 // completed by block 0).
-__device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, int32_t *Drow, uint32_t *cnt8, int v,
+__device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, int32_t *Drow, uint32_t *cnt, int v,
                                            int dv, int u, int du, int s) {
     const int val = dv - du;
     Drow[u] = val;
@@ -1347,7 +1347,7 @@ __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, in
     atomicOr(&mrow[u >> 5], 1u << (u & 31));
     if (u != s) {
         atomicOr(&fs.mask[(size_t)u * fs.MW + (v >> 5)], 1u << (v & 31));
-        atomicAdd(&cnt8[u >> 2], 1u << ((u & 3) * 8));
+        atomicAdd(&cnt[u >> 2], 1u << ((u & 3) * 8));
     }
 }
 
@@ -1379,22 +1379,10 @@ __device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t 
     }
 }
 
-// The link fill of one block: pixels chunk * kFillLanes .. + kFillLanes.
-// smem: link_fill_lds(N) bytes: L (N words), then a region that first holds
-// the tree words and then G, the byte counters and the new-pair flags.
-__device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
-                                 int chunk) {
-    const FrCtl *ctl = fs.ctl;
-    const int64_t t0 = fs.trace ? trace_clock() : 0;
-    const int s = ctl->s, N = fs.N;
-    uint32_t *L = smem;
-    uint32_t *T = smem + al4w(N);
-    uint16_t *G = (uint16_t *)T;
-    uint32_t *C8 = T + al4w((N + 1) / 2);
-    uint32_t *FL = C8 + al4w((N + 3) / 4);
-    copy_to_lds(T, tree, N);
-    __syncthreads();
-    // U pixels per thread at a time, so that their dependent LDS reads overlap
+// L[x] = parent(x) | (d(x) - d(parent(x))) << 16 (kNoId at the root) from the
+// tree words T, both in LDS; U pixels per thread at a time, so that their
+// dependent LDS reads overlap.
+__device__ void build_parent_links(const uint32_t *T, uint32_t *L, int N, int W) {
     constexpr int U = 8;
     const int nb = (int)blockDim.x;
     for (int base = threadIdx.x; base < N; base += nb * U) {
@@ -1414,10 +1402,12 @@ __device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W,
             if (base + k * nb < N)
                 L[base + k * nb] = p[k] < 0 ? kNoId : ((uint32_t)p[k] | ((uint32_t)(tw_dist(t[k]) - tw_dist(tp[k])) << 16));
     }
-    const int v = chunk * kFillLanes + (int)threadIdx.x;
-    const bool walker = threadIdx.x < kFillLanes && v < N && v != s && !((fs.full[v >> 5] >> (v & 31)) & 1u);
-    const int dv = walker ? tw_dist(T[v]) : 0;
-    __syncthreads();  // the tree words are no longer needed: their space takes G, counters and flags
+}
+
+// G[x] = grandparent(x) (kNoId: none) from L.
+__device__ void build_grandparents(const uint32_t *L, uint16_t *G, int N) {
+    constexpr int U = 8;
+    const int nb = (int)blockDim.x;
     for (int base = threadIdx.x; base < N; base += nb * U) {
         uint32_t p[U], g[U];
 #pragma unroll
@@ -1428,6 +1418,30 @@ __device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W,
         for (int k = 0; k < U; ++k)
             if (base + k * nb < N) G[base + k * nb] = (uint16_t)g[k];
     }
+}
+
+// The link fill of one block: pixels chunk * kFillLanes .. + kFillLanes.
+// smem: link_fill_lds(N) bytes: L (N words), then a region that first holds
+// the tree words and then G, the byte counters and the new-pair flags.
+__device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
+                                 int chunk) {
+    const FrCtl *ctl = fs.ctl;
+    const int64_t t0 = fs.trace ? trace_clock() : 0;
+    const int s = ctl->s, N = fs.N;
+    uint32_t *L = smem;
+    uint32_t *T = smem + al4w(N);
+    uint16_t *G = (uint16_t *)T;
+    uint32_t *C8 = T + al4w((N + 1) / 2);
+    uint32_t *FL = C8 + al4w((N + 3) / 4);
+    copy_to_lds(T, tree, N);
+    __syncthreads();
+    build_parent_links(T, L, N, W);
+    const int v = chunk * kFillLanes + (int)threadIdx.x;
+    // a complete row has nothing left to fill, whenever it became complete
+    const bool walker = threadIdx.x < kFillLanes && v < N && v != s && fs.count[v] < N;
+    const int dv = walker ? tw_dist(T[v]) : 0;
+    __syncthreads();  // the tree words are no longer needed: their space takes G, counters and flags
+    build_grandparents(L, G, N);
     for (int i = threadIdx.x; i < (N + 3) / 4; i += blockDim.x) C8[i] = 0;
     __syncthreads();
     WalkOut o{0, -1, 0};
