@@ -95,7 +95,8 @@ typedef struct {
                                launch of its two loop kernels with events                 */
     float    ms_step_kernels; /* sum of durations of the select+propagate launches        */
     float    ms_fill_kernels; /* sum of durations of the redundancy-fill launches         */
-    int32_t  _pad2;
+    int32_t  graph_replays; /* tree modes: chunks of loop steps replayed as a HIP graph
+                               (captured once per call; GAPD_FR_GRAPH=0 turns it off)    */
     int64_t  n_prop_speculative; /* filling-rate mode: propagations computed ahead for
                                     likely next sources (not counted in n_prop)          */
     int64_t  n_cache_hits;  /* filling-rate steps whose propagation was such a tree, taken

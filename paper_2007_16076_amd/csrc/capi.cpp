@@ -70,6 +70,30 @@ int max_rounds_for(int N) {
     return std::max(1, std::min(cap, N + 1));
 }
 
+StepGraph::~StepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+}
+
+bool StepGraph::capture(int n, const std::function<hipError_t(hipStream_t)> &step) {
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { cs = nullptr; return false; }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < n && le == hipSuccess; ++i) le = step(cs);
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    (void)hipGetLastError();  // a failed capture leaves no error for later calls
+    if (le != hipSuccess || ce != hipSuccess || !graph) return false;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        exec = nullptr;
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+bool use_step_graphs() { return env_int("GAPD_FR_GRAPH", 1) != 0; }
+
 }  // namespace gapd
 
 struct gapd_ctx {
@@ -218,6 +242,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    s.graph_replays = 0;
     int st = GAPD_OK;
     hipEvent_t e0, e1, e2;
     HIP_OR_FAIL(ctx, hipEventCreate(&e0));
@@ -255,7 +280,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         FrCtl hc{};
         float kt[2] = {0.f, 0.f};
         st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, e1, hc, ctx->err, ctx->poisoned,
-                              s.time_kernels ? kt : nullptr);
+                              s.time_kernels ? kt : nullptr, &s.graph_replays);
         s.ms_step_kernels = kt[0];
         s.ms_fill_kernels = kt[1];
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
@@ -355,6 +380,7 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    s.graph_replays = 0;
     if (mode == GAPD_MODE_NAIVE) {
         // no scratch: the naive method only needs the context's control block
         st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
@@ -382,7 +408,8 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     if (fs.trace)
         HIP_OR_FAIL(ctx, hipMemsetAsync(fs.trace, 0, sizeof(int64_t) * kTraceFields * (size_t)ctx->N, ctx->stream));
     FrCtl hc{};
-    st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, nullptr, hc, ctx->err, ctx->poisoned);
+    st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, nullptr, hc, ctx->err, ctx->poisoned, nullptr,
+                          &s.graph_replays);
     s.n_prop = hc.n_prop;
     s.rounds = hc.rounds;
     s.n_prop_speculative = hc.spec_props;
@@ -438,7 +465,7 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
 }
 
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned, float *kt) {
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt, int *graph_replays) {
     const int N = g.N;
     auto bad = [&](hipError_t e, const char *where) {
         poisoned = true;
@@ -476,12 +503,25 @@ int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream
     } ev_free{ev};
     int64_t enq = 0;
     int status = GAPD_OK;
+    // After the first chunk (direct launches, which also set the kernels'
+    // attributes) the chunk is captured once into a graph and replayed.
+    StepGraph sg;
+    bool graphs = !kt && use_step_graphs();
     for (;;) {
-        for (int i = 0; i < chunk; ++i) {
-            if (kt) (void)hipEventRecord(ev[3 * i], stream);
-            e = launch_fr_step(g, fs, max_rounds, stream, kt ? ev[3 * i + 1] : nullptr);
-            if (e != hipSuccess) return bad(e, "filling-rate step");
-            if (kt) (void)hipEventRecord(ev[3 * i + 2], stream);
+        if (graphs && enq > 0 && !sg.exec &&
+            !sg.capture(chunk, [&](hipStream_t s) { return launch_fr_step(g, fs, max_rounds, s, nullptr); }))
+            graphs = false;  // capture refused: keep launching directly
+        if (graphs && sg.exec) {
+            e = hipGraphLaunch(sg.exec, stream);
+            if (e != hipSuccess) return bad(e, "filling-rate step graph");
+            if (graph_replays) ++*graph_replays;
+        } else {
+            for (int i = 0; i < chunk; ++i) {
+                if (kt) (void)hipEventRecord(ev[3 * i], stream);
+                e = launch_fr_step(g, fs, max_rounds, stream, kt ? ev[3 * i + 1] : nullptr);
+                if (e != hipSuccess) return bad(e, "filling-rate step");
+                if (kt) (void)hipEventRecord(ev[3 * i + 2], stream);
+            }
         }
         e = hipMemcpyAsync(&hc, fs.ctl, sizeof(FrCtl), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -640,10 +680,18 @@ int gapd_all_pairs_batched(const uint8_t *images_packed, const int32_t *H, const
             e = launch_fr_batched_setup(bimg_dev, B, max_line, maxN, lds, conn, max_rounds, st);
             const int chunk = std::max(1, env_int("GAPD_FR_CHUNK", 64));
             int64_t enq = 0;
+            StepGraph sg;  // as in run_filling_rate: the chunk replayed as a graph after the first
+            bool graphs = use_step_graphs();
+            auto step = [&](hipStream_t s) {
+                return launch_fr_batched_step(bimg_dev, B, max_line, maxN, lds, wbytes, conn, max_rounds,
+                                              &ctl_dev->done, s);
+            };
             while (e == hipSuccess) {
-                for (int i = 0; i < chunk && e == hipSuccess; ++i)
-                    e = launch_fr_batched_step(bimg_dev, B, max_line, maxN, lds, wbytes, conn, max_rounds,
-                                               &ctl_dev->done, st);
+                if (graphs && enq > 0 && !sg.exec && !sg.capture(chunk, step)) graphs = false;
+                if (graphs && sg.exec)
+                    e = hipGraphLaunch(sg.exec, st);
+                else
+                    for (int i = 0; i < chunk && e == hipSuccess; ++i) e = step(st);
                 enq += chunk;
                 FrCtl hc{};
                 if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl_dev, sizeof(FrCtl), hipMemcpyDeviceToHost, st);

@@ -1,6 +1,7 @@
 // Host-side helpers shared by the C ABI (capi.cpp) and the server (server.cpp).
 #pragma once
 
+#include <functional>
 #include <string>
 
 #include "gapd_internal.h"
@@ -12,6 +13,20 @@ extern thread_local std::string g_create_error;
 int env_int(const char *name, int dflt);
 int validate_image(const uint8_t *img, int H, int W, int C, int conn, int wmode, std::string &why);
 int max_rounds_for(int N);
+
+// A chunk of loop steps recorded once from a private stream (capture only,
+// nothing runs there) and replayed on the caller's stream.  Only kernel
+// launches are recorded: no memset or copy.
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = nullptr;
+    ~StepGraph();
+    // Record n calls of step; false (and nothing to replay) if HIP refused.
+    bool capture(int n, const std::function<hipError_t(hipStream_t)> &step);
+};
+// Whether loop chunks are replayed as graphs (GAPD_FR_GRAPH=0 turns it off).
+bool use_step_graphs();
 
 // Longest image side the tree-based methods accept on one image: their step
 // kernel keeps the distance field in LDS.
@@ -29,6 +44,6 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
 // durations of the launches that did work are returned in kt[0] (select +
 // propagate) and kt[1] (fill).
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned, float *kt = nullptr);
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt = nullptr, int *graph_replays = nullptr);
 
 }  // namespace gapd

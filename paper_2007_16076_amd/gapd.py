@@ -44,7 +44,7 @@ class Stats(ctypes.Structure):
                 ("sources_out", ctypes.c_void_p), ("filled_out", ctypes.c_void_p),
                 ("ms_total", ctypes.c_float), ("ms_setup", ctypes.c_float), ("ms_kernel", ctypes.c_float),
                 ("time_kernels", ctypes.c_int32), ("ms_step_kernels", ctypes.c_float),
-                ("ms_fill_kernels", ctypes.c_float), ("_pad2", ctypes.c_int32),
+                ("ms_fill_kernels", ctypes.c_float), ("graph_replays", ctypes.c_int32),
                 ("n_prop_speculative", ctypes.c_int64), ("n_cache_hits", ctypes.c_int64),
                 ("step_trace", ctypes.c_void_p)]
 
@@ -154,6 +154,7 @@ class AllPairsStats:
     ms_fill_kernels: float
     n_prop_speculative: int = 0
     n_cache_hits: int = 0
+    graph_replays: int = 0
 
 
 class Context:
@@ -261,7 +262,7 @@ class Context:
 def _stats(st) -> "AllPairsStats":
     return AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup,
                          st.ms_kernel, st.ms_step_kernels, st.ms_fill_kernels, st.n_prop_speculative,
-                         st.n_cache_hits)
+                         st.n_cache_hits, st.graph_replays)
 
 
 def batched_workspace_size(shapes, C: int = 1, conn: int = CONN4, mode: int = MODE_NAIVE) -> int:

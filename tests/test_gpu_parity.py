@@ -234,6 +234,40 @@ def test_batched_matches_solo(G, torch_mod, oracle_lib, mode):
             assert nprop[b] == ref.n_prop
 
 
+@pytest.mark.parametrize("chunk", ["3", "64"])
+def test_step_graph_replay_equals_direct(G, torch_mod, monkeypatch, chunk):
+    """Chunks of loop steps replayed as a HIP graph give the run of direct
+    launches: the same D, source sequence and a(t) after every step, that is
+    after every replay (eager polls and synchronisations between replays),
+    for one image and for a batch."""
+    import synth
+    torch = torch_mod
+    monkeypatch.setenv("GAPD_FR_CHUNK", chunk)
+    img = synth.blob_image(np.random.default_rng(21), 40, 44)
+    res = {}
+    for on in ("0", "1"):
+        monkeypatch.setenv("GAPD_FR_GRAPH", on)
+        res[on] = run_fr(G, torch, img, 4)
+    say("graph replays", chunk, res["1"][3].graph_replays)
+    assert res["0"][3].graph_replays == 0 and res["1"][3].graph_replays > 0
+    for k in range(3):
+        assert np.array_equal(res["0"][k], res["1"][k])
+    rng = np.random.default_rng(22)
+    imgs = [rng.integers(1, 256, size=(int(rng.integers(8, 40)), int(rng.integers(8, 40))), dtype=np.uint8)
+            for _ in range(6)]
+    offs = G.pack_offsets([im.shape for im in imgs])
+    nseq = sum(im.size for im in imgs)
+    outs = {}
+    for on in ("0", "1"):
+        monkeypatch.setenv("GAPD_FR_GRAPH", on)
+        seq = torch.full((nseq,), -7, dtype=torch.int32, device="cuda")
+        out, _, nprop = G.all_pairs_batched(imgs, mode=G.MODE_TREE_FILL_FR, out=poisoned(torch, int(offs[-1])),
+                                            offsets=offs, sources_out=seq)
+        outs[on] = (out.cpu().numpy(), nprop.copy(), seq.cpu().numpy())
+    for k in range(3):
+        assert np.array_equal(outs["0"][k], outs["1"][k])
+
+
 # ------------------------------------------------------------------------------------- errors, determinism
 
 def test_round_cap_reports_no_convergence(G, torch_mod, monkeypatch):
