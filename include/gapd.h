@@ -194,6 +194,36 @@ int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *
  * context's stream). */
 int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st);
 
+/* Launch shapes chosen by gapd_autotune. */
+typedef struct {
+    int32_t fill_lanes;   /* tree modes: walking threads per fill workgroup (128 or 256)   */
+    int32_t walk_pf;      /* tree modes: ancestor pairs in flight per walk (8 or 16)       */
+    int32_t spec_cap;     /* tree modes: new speculative propagations per step (16 or 32)  */
+    int32_t naive_pfw;    /* naive mode: lines of edge weights each sweep loads ahead (4, 8) */
+    float   ms;           /* the chosen shapes' call time                                  */
+    float   ms_default;   /* the default shapes' call time                                 */
+    int32_t candidates;   /* shapes timed                                                   */
+    int32_t _pad;
+} gapd_tuning;
+
+/* Time the candidate launch shapes of `mode` (GAPD_MODE_NAIVE,
+ * GAPD_MODE_TREE_FILL_FR or GAPD_MODE_TREE_FILL_EXTREMA) with one whole
+ * gapd_all_pairs call each on this context's image (after one warm-up call;
+ * the tree modes need the workspace), and keep the fastest, in the process
+ * and in a JSON cache file (GAPD_TUNE_FILE, else gapd_tune.json beside
+ * libgapd.so), keyed by (device architecture, H x W x C, connectivity,
+ * mode).  Every later call on an image of that key uses them.  The results
+ * (D and the rest) are the same for every shape.  out: DEVICE N*N int32
+ * that receives the calls' D.  best: nullable host struct.  Other modes give
+ * GAPD_EINVAL. */
+int gapd_autotune(gapd_ctx *ctx, int mode, int32_t *out, gapd_tuning *best);
+
+/* Pin the launch shapes that `mode` uses on images of this context's key,
+ * for the rest of the process (the cache file is not written).  Only the
+ * first four fields of t are read; values outside fill_lanes {128, 256},
+ * walk_pf {8, 16}, spec_cap 1..32, naive_pfw {4, 8} give GAPD_EINVAL. */
+int gapd_set_tuning(gapd_ctx *ctx, int mode, const gapd_tuning *t);
+
 /* Release the context and its device memory (not the caller's buffers). */
 void gapd_destroy(gapd_ctx *ctx);
 

@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libgapd.so")
 FR_PARTS = [(c, s) for c in (4, 8) for s in (32, 64, 128, 192)]
 UNITS = [("k_fr.hip", f"k_fr_{c}_{s}", [f"-DGAPD_CONN={c}", f"-DGAPD_S={s}"]) for c, s in FR_PARTS] + \
         [(f, f.rsplit(".", 1)[0], []) for f in
-         ("k_misc.hip", "k_naive.hip", "k_frb.hip", "k_graph.hip", "capi.cpp", "server.cpp", "graph.cpp")]
+         ("k_misc.hip", "k_naive.hip", "k_frb.hip", "k_graph.hip", "capi.cpp", "server.cpp", "graph.cpp",
+          "tune.cpp")]
 ARCH = os.environ.get("GAPD_OFFLOAD_ARCH", "gfx950")
 
 

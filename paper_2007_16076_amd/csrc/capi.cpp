@@ -236,8 +236,18 @@ int gapd_sssp(gapd_ctx *ctx, const int32_t *sources, int K, int32_t *out) {
 
 namespace {
 
-// One all-pairs call: the naive method (rule < 0) or a tree-based method.
-int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_t *out, gapd_stats *stp) {
+// The API mode of a rule (-1: the naive method).
+int mode_of_rule(int rule) {
+    return rule < 0 ? GAPD_MODE_NAIVE
+                    : rule == kRuleFilling ? GAPD_MODE_TREE_FILL_FR
+                                           : rule == kRuleExtrema ? GAPD_MODE_TREE_FILL_EXTREMA : GAPD_MODE_TREE_FILL_SPIRAL;
+}
+
+// One all-pairs call: the naive method (rule < 0) or a tree-based method,
+// with the autotuned launch shapes of this image and method, or *force.
+int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_t *out, gapd_stats *stp,
+                   const Tuning *force = nullptr) {
+    const Tuning tune = force ? *force : tuning_for(tune_key(ctx->H, ctx->W, ctx->C, ctx->conn, mode_of_rule(rule)));
     gapd_stats local{};
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
@@ -255,7 +265,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
     HIP_OR_FAIL(ctx, hipEventRecord(e0, ctx->stream));
     if (rule < 0) {
         st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
-                      ctx->poisoned, &s.rounds, &s.ms_kernel);
+                      ctx->poisoned, &s.rounds, &s.ms_kernel, tune.naive_pfw);
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = ctx->N;
@@ -270,6 +280,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         fs.rule = rule;
         fs.rep_h = h;
         fs.draws = draws;
+        fs.spec_cap = tune.spec_cap;
         if (rule == kRuleSpiral) fs.cache = nullptr;  // no speculation on random draws
         fs.D = out;
         fs.seq_out = s.sources_out;
@@ -280,7 +291,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         FrCtl hc{};
         float kt[2] = {0.f, 0.f};
         st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, e1, hc, ctx->err, ctx->poisoned,
-                              s.time_kernels ? kt : nullptr, &s.graph_replays);
+                              s.time_kernels ? kt : nullptr, &s.graph_replays, tune);
         s.ms_step_kernels = kt[0];
         s.ms_fill_kernels = kt[1];
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
@@ -313,6 +324,80 @@ int gapd_all_pairs(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *stp) {
         return fail(ctx, GAPD_EINVAL, "unknown mode");
     const int rule = mode == GAPD_MODE_NAIVE ? -1 : mode == GAPD_MODE_TREE_FILL_FR ? kRuleFilling : kRuleExtrema;
     return all_pairs_impl(ctx, rule, 0, nullptr, out, stp);
+}
+
+int gapd_autotune(gapd_ctx *ctx, int mode, int32_t *out, gapd_tuning *best) {
+    int st = ctx_check(ctx);
+    if (st) return st;
+    if (!out) return fail(ctx, GAPD_EINVAL, "out is null");
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return fail(ctx, GAPD_EINVAL, "only the naive, filling-rate and extrema modes are tuned");
+    const int rule = mode == GAPD_MODE_NAIVE ? -1 : mode == GAPD_MODE_TREE_FILL_FR ? kRuleFilling : kRuleExtrema;
+    // The candidates, the defaults first.
+    std::vector<Tuning> cands;
+    if (mode == GAPD_MODE_NAIVE) {
+        for (int pfw : {4, 8}) {
+            Tuning t;
+            t.naive_pfw = pfw;
+            cands.push_back(t);
+        }
+    } else {
+        for (int lanes : {kFillLanes, 256})
+            for (int pf : {16, 8})
+                for (int cap : {kSpecK, kSpecK / 2}) {
+                    Tuning t;
+                    t.fill_lanes = lanes;
+                    t.walk_pf = pf;
+                    t.spec_cap = cap;
+                    cands.push_back(t);
+                }
+    }
+    gapd_stats s{};
+    st = all_pairs_impl(ctx, rule, 0, nullptr, out, &s, &cands[0]);  // warm-up
+    if (st) return st;
+    float best_ms = 0, default_ms = 0;
+    size_t bi = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        gapd_stats t{};
+        st = all_pairs_impl(ctx, rule, 0, nullptr, out, &t, &cands[i]);
+        if (st) return st;
+        if (i == 0) default_ms = t.ms_total;
+        if (i == 0 || t.ms_total < best_ms) {
+            best_ms = t.ms_total;
+            bi = i;
+        }
+    }
+    store_tuning(tune_key(ctx->H, ctx->W, ctx->C, ctx->conn, mode), cands[bi], best_ms);
+    if (best) {
+        best->fill_lanes = cands[bi].fill_lanes;
+        best->walk_pf = cands[bi].walk_pf;
+        best->spec_cap = cands[bi].spec_cap;
+        best->naive_pfw = cands[bi].naive_pfw;
+        best->ms = best_ms;
+        best->ms_default = default_ms;
+        best->candidates = (int32_t)cands.size();
+        best->_pad = 0;
+    }
+    return GAPD_OK;
+}
+
+int gapd_set_tuning(gapd_ctx *ctx, int mode, const gapd_tuning *t) {
+    int st = ctx_check(ctx);
+    if (st) return st;
+    if (!t) return fail(ctx, GAPD_EINVAL, "tuning is null");
+    if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
+        return fail(ctx, GAPD_EINVAL, "only the naive, filling-rate and extrema modes are tuned");
+    if ((t->fill_lanes != 128 && t->fill_lanes != 256) || (t->walk_pf != 8 && t->walk_pf != 16) ||
+        t->spec_cap < 1 || t->spec_cap > kSpecK || (t->naive_pfw != 4 && t->naive_pfw != 8))
+        return fail(ctx, GAPD_EINVAL, "unsupported launch shapes (fill_lanes 128|256, walk_pf 8|16, spec_cap 1..32, "
+                                      "naive_pfw 4|8)");
+    Tuning x;
+    x.fill_lanes = t->fill_lanes;
+    x.walk_pf = t->walk_pf;
+    x.spec_cap = t->spec_cap;
+    x.naive_pfw = t->naive_pfw;
+    store_tuning(tune_key(ctx->H, ctx->W, ctx->C, ctx->conn, mode), x, 0.0, false);
+    return GAPD_OK;
 }
 
 int gapd_all_pairs_spiral(gapd_ctx *ctx, int h, const uint32_t *draws, int32_t *out, gapd_stats *stp) {
@@ -407,9 +492,11 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     fs.trace = s.step_trace;
     if (fs.trace)
         HIP_OR_FAIL(ctx, hipMemsetAsync(fs.trace, 0, sizeof(int64_t) * kTraceFields * (size_t)ctx->N, ctx->stream));
+    const Tuning tune = tuning_for(tune_key(ctx->H, ctx->W, ctx->C, ctx->conn, mode));
+    fs.spec_cap = tune.spec_cap;
     FrCtl hc{};
     st = run_filling_rate(ctx->g, fs, ctx->max_rounds, ctx->stream, nullptr, hc, ctx->err, ctx->poisoned, nullptr,
-                          &s.graph_replays);
+                          &s.graph_replays, tune);
     s.n_prop = hc.n_prop;
     s.rounds = hc.rounds;
     s.n_prop_speculative = hc.spec_props;
@@ -433,7 +520,7 @@ void gapd_destroy(gapd_ctx *ctx) {
 namespace gapd {
 
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
-             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel) {
+             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel, int pfw) {
     // Launch errors are read with hipGetLastError: drop one that an earlier,
     // unrelated call left pending so it is not taken for ours.
     (void)hipGetLastError();
@@ -443,7 +530,7 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
     }
     hipError_t e = hipMemsetAsync(ctl, 0, sizeof(FrCtl), stream);
     if (e == hipSuccess && ms_kernel) e = hipEventRecord(k0, stream);
-    if (e == hipSuccess) e = launch_relax_rows(g, src_list, src_base, K, out, max_rounds, ctl, stream);
+    if (e == hipSuccess) e = launch_relax_rows(g, src_list, src_base, K, out, max_rounds, ctl, stream, pfw);
     if (e == hipSuccess && ms_kernel) e = hipEventRecord(k1, stream);
     FrCtl hc{};
     if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl, sizeof(FrCtl), hipMemcpyDeviceToHost, stream);
@@ -465,7 +552,8 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
 }
 
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned, float *kt, int *graph_replays) {
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt, int *graph_replays,
+                     const Tuning &tune) {
     const int N = g.N;
     auto bad = [&](hipError_t e, const char *where) {
         poisoned = true;
@@ -509,7 +597,7 @@ int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream
     bool graphs = !kt && use_step_graphs();
     for (;;) {
         if (graphs && enq > 0 && !sg.exec &&
-            !sg.capture(chunk, [&](hipStream_t s) { return launch_fr_step(g, fs, max_rounds, s, nullptr); }))
+            !sg.capture(chunk, [&](hipStream_t s) { return launch_fr_step(g, fs, max_rounds, s, nullptr, tune); }))
             graphs = false;  // capture refused: keep launching directly
         if (graphs && sg.exec) {
             e = hipGraphLaunch(sg.exec, stream);
@@ -518,7 +606,7 @@ int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream
         } else {
             for (int i = 0; i < chunk; ++i) {
                 if (kt) (void)hipEventRecord(ev[3 * i], stream);
-                e = launch_fr_step(g, fs, max_rounds, stream, kt ? ev[3 * i + 1] : nullptr);
+                e = launch_fr_step(g, fs, max_rounds, stream, kt ? ev[3 * i + 1] : nullptr, tune);
                 if (e != hipSuccess) return bad(e, "filling-rate step");
                 if (kt) (void)hipEventRecord(ev[3 * i + 2], stream);
             }

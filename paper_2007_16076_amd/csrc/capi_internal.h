@@ -34,9 +34,17 @@ constexpr int kTreeMaxSide = 192;
 inline bool tree_methods_fit(int H, int W) { return H <= kTreeMaxSide && W <= kTreeMaxSide; }
 
 // Propagations from K sources into K rows of out; synchronises the stream.
+// pfw: the sweeps' weight prefetch depth (0: default).
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
              hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr,
-             float *ms_kernel = nullptr);
+             float *ms_kernel = nullptr, int pfw = 0);
+
+// Autotuned launch shapes (tune.cpp): the cache key of an image and method,
+// and the cached shapes for it (defaults when the cache has none).
+std::string tune_key(int H, int W, int C, int conn, int mode);
+Tuning tuning_for(const std::string &key);
+// save: also rewrite the cache file (else this process only).
+void store_tuning(const std::string &key, const Tuning &t, double ms, bool save = true);
 
 // The filling-rate method on one image (workspace fs, output fs.D); the
 // final control block is copied to hc.  Synchronises the stream.
@@ -44,6 +52,7 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
 // durations of the launches that did work are returned in kt[0] (select +
 // propagate) and kt[1] (fill).
 int run_filling_rate(const GImg &g, const FrState &fs, int max_rounds, hipStream_t stream, hipEvent_t setup_done,
-                     FrCtl &hc, std::string &err, bool &poisoned, float *kt = nullptr, int *graph_replays = nullptr);
+                     FrCtl &hc, std::string &err, bool &poisoned, float *kt = nullptr, int *graph_replays = nullptr,
+                     const Tuning &tune = Tuning());
 
 }  // namespace gapd

@@ -938,7 +938,9 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
     if (threadIdx.x < kSpecK) {
         const int j = threadIdx.x;
         bool take = false;
-        if (j >= nr) {
+        // new candidates: at most spec_cap of them (running pieces continue regardless)
+        const int cap = fs.spec_cap > 0 ? fs.spec_cap : kSpecK;
+        if (j >= nr && j - nr < cap) {
             const uint64_t ck = keys[128 + (j - nr)];
             const uint64_t keep = skeys[j - nr] >> 8;
             take = ck != kNoKey && keep != kPinned && (keep < 2 || key_heur<RULE>(ck) < kTop - (keep - 2));
@@ -1264,9 +1266,9 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
 //           d(s,u) = d(s,v) - (edge weights on the way), and for each new pair
 //           write D(u,v) = D(v,u) = d(s,v) - d(s,u), set both matrix bits and
 //           count it.  Stores and atomics are fire-and-forget.
-// Counts: the block sums the increments of the ancestors in LDS (one byte
-// per pixel: at most kFillLanes per block) and adds them once; row v adds
-// its own.  The complete-row bitmap is rebuilt from the counts by the next
+// Counts: the block sums the increments of the ancestors in LDS (8-bit
+// counters for up to 255 walking threads per block, else 16-bit) and adds
+// them once; row v adds its own.  The complete-row bitmap is rebuilt from the counts by the next
 // select.
 // ---------------------------------------------------------------------------------------------
 struct WalkOut {
@@ -1337,20 +1339,23 @@ __device__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint3
 }
 
 // Pair (u, v) is new: D(u,v) = D(v,u) = dv - du, both matrix bits, counts
-// (u's in the block's byte counters, never the source's: its row is
-// completed by block 0).
+// (u's in the block's LDS counters, 1 << CS per word, never the source's:
+// its row is completed by block 0).
+template <int CS>
 __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, int32_t *Drow, uint32_t *cnt, int v,
                                            int dv, int u, int du, int s) {
+    constexpr int kPer = 1 << CS, kBits = 32 / kPer;
     const int val = dv - du;
     Drow[u] = val;
     fs.D[(size_t)u * fs.N + v] = val;
     atomicOr(&mrow[u >> 5], 1u << (u & 31));
     if (u != s) {
         atomicOr(&fs.mask[(size_t)u * fs.MW + (v >> 5)], 1u << (v & 31));
-        atomicAdd(&cnt[u >> 2], 1u << ((u & 3) * 8));
+        atomicAdd(&cnt[u >> CS], 1u << ((u & (kPer - 1)) * kBits));
     }
 }
 
+template <int CS>
 __device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t *G, const uint32_t *flags,
                            uint32_t *cnt8, int v, int dv, int last, int s) {
     constexpr int kCap = kFillFlagWords * 32;
@@ -1370,10 +1375,10 @@ __device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t 
             na = !((mrow[a >> 5] >> (a & 31)) & 1u);
             nb = b != (int)kNoId && !((mrow[b >> 5] >> (b & 31)) & 1u);
         }
-        if (na) write_pair(fs, mrow, Drow, cnt8, v, dv, a, da, s);
+        if (na) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, a, da, s);
         if (b == (int)kNoId) break;
         const int db = da - (int)(L[a] >> 16);
-        if (nb) write_pair(fs, mrow, Drow, cnt8, v, dv, b, db, s);
+        if (nb) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, b, db, s);
         cur = b;
         dcur = db;
     }
@@ -1420,44 +1425,49 @@ __device__ void build_grandparents(const uint32_t *L, uint16_t *G, int N) {
     }
 }
 
-// The link fill of one block: pixels chunk * kFillLanes .. + kFillLanes.
-// smem: link_fill_lds(N) bytes: L (N words), then a region that first holds
-// the tree words and then G, the byte counters and the new-pair flags.
+// The link fill of one block: pixels chunk * kLanes .. + kLanes, PF pairs of
+// ancestors in flight per walk.  smem: link_fill_lds(N, kLanes) bytes: L (N
+// words), then a region that first holds the tree words and then G, the
+// ancestor counters and the new-pair flags.
+template <int kLanes = kFillLanes, int PF = 16>
 __device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
                                  int chunk) {
+    constexpr int CS = fill_cnt_shift(kLanes), kPer = 1 << CS, kBits = 32 / kPer;
+    constexpr uint32_t kCntMask = (1u << kBits) - 1u;
     const FrCtl *ctl = fs.ctl;
     const int64_t t0 = fs.trace ? trace_clock() : 0;
     const int s = ctl->s, N = fs.N;
+    const int ncw = (N + kPer - 1) / kPer;  // counter words
     uint32_t *L = smem;
     uint32_t *T = smem + al4w(N);
     uint16_t *G = (uint16_t *)T;
     uint32_t *C8 = T + al4w((N + 1) / 2);
-    uint32_t *FL = C8 + al4w((N + 3) / 4);
+    uint32_t *FL = C8 + al4w(ncw);
     copy_to_lds(T, tree, N);
     __syncthreads();
     build_parent_links(T, L, N, W);
-    const int v = chunk * kFillLanes + (int)threadIdx.x;
+    const int v = chunk * kLanes + (int)threadIdx.x;
     // a complete row has nothing left to fill, whenever it became complete
-    const bool walker = threadIdx.x < kFillLanes && v < N && v != s && fs.count[v] < N;
+    const bool walker = (int)threadIdx.x < kLanes && v < N && v != s && fs.count[v] < N;
     const int dv = walker ? tw_dist(T[v]) : 0;
     __syncthreads();  // the tree words are no longer needed: their space takes G, counters and flags
     build_grandparents(L, G, N);
-    for (int i = threadIdx.x; i < (N + 3) / 4; i += blockDim.x) C8[i] = 0;
+    for (int i = threadIdx.x; i < ncw; i += blockDim.x) C8[i] = 0;
     __syncthreads();
     WalkOut o{0, -1, 0};
     uint32_t *flags = FL + (size_t)threadIdx.x * kFillFlagWords;
-    if (walker) o = walk_detect<16>(L, G, fs.mask + (size_t)v * fs.MW, v, flags);
+    if (walker) o = walk_detect<PF>(L, G, fs.mask + (size_t)v * fs.MW, v, flags);
     if (o.nnew) {
-        walk_write(fs, L, G, flags, C8, v, dv, o.last, s);
+        walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s);
         atomicAdd(&fs.count[v], o.nnew);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < (N + 3) / 4; i += blockDim.x) {
+    for (int i = threadIdx.x; i < ncw; i += blockDim.x) {
         const uint32_t c = C8[i];
         if (c) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if ((c >> (8 * j)) & 255u) atomicAdd(&fs.count[4 * i + j], (int)((c >> (8 * j)) & 255u));
+            for (int j = 0; j < kPer; ++j)
+                if ((c >> (kBits * j)) & kCntMask) atomicAdd(&fs.count[kPer * i + j], (int)((c >> (kBits * j)) & kCntMask));
         }
     }
     const int64_t tot = block_sum_i64(o.nnew, red);

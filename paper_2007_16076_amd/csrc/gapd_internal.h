@@ -81,6 +81,7 @@ struct FrState {
     int H, W;
     int rule;                  // kRule*
     int rep_h;                 // spiral: repulsion distance (<= 1: none)
+    int spec_cap;              // new speculative propagations planned per step, at most (0: kSpecK)
     const uint32_t *draws;     // spiral: N uniform 32-bit draws, one per selection
     int32_t *sp_in;            // spiral: membership in S by position along the turn
     uint32_t *mask;            // N * MW bits: D_mrk
@@ -130,18 +131,30 @@ enum TraceField {
 // The link fill (the redundancy fill with 16-bit pixel ids in LDS tables).
 constexpr uint32_t kNoId = 0xFFFFu;   // no such pixel (the root's parent)
 __host__ __device__ inline size_t al4w(size_t n) { return (n + 3) & ~size_t(3); }
-// Walking threads per block of the link fill, and 32-bit words of new-pair
-// flags each keeps in LDS (one flag per ancestor; longer walks fall back to
-// re-reading the filled-pairs matrix).
+// Walking threads per block of the link fill (the default; the autotuner may
+// pick 256), and 32-bit words of new-pair flags each keeps in LDS (one flag
+// per ancestor; longer walks fall back to re-reading the filled-pairs matrix).
 constexpr int kFillLanes = 128;
 constexpr int kFillFlagWords = 12;
+// Per-pixel counters of a link-fill block: one ancestor gains at most one
+// new pair per walking thread, so 8 bits hold up to 255 walkers and 16 bits
+// the rest.  log2 of the counters per 32-bit word:
+__host__ __device__ constexpr int fill_cnt_shift(int lanes) { return lanes < 256 ? 2 : 1; }
 // LDS of a link-fill block: L (N words), then a region that holds the tree
-// words (N words) and afterwards G (N uint16), the byte counters (N bytes)
-// and the flags.
-__host__ __device__ inline size_t link_fill_lds(int N) {
-    const size_t later = al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + 3) / 4) + (size_t)kFillLanes * kFillFlagWords;
+// words (N words) and afterwards G (N uint16), the counters and the flags.
+__host__ __device__ inline size_t link_fill_lds(int N, int lanes = kFillLanes) {
+    const size_t per = (size_t)1 << fill_cnt_shift(lanes);
+    const size_t later = al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + per - 1) / per) + (size_t)lanes * kFillFlagWords;
     return 4 * (al4w(N) + (al4w(N) > later ? al4w(N) : later));
 }
+
+// Launch shapes the autotuner chooses (include/gapd.h, gapd_autotune).
+struct Tuning {
+    int fill_lanes = kFillLanes;  // link fill: walking threads per block (128 or 256)
+    int walk_pf = 16;             // link fill: ancestor pairs in flight per walk (8 or 16)
+    int spec_cap = 32;            // tree modes: new speculative propagations per step (<= kSpecK)
+    int naive_pfw = 4;            // naive: lines of weights the sweeps load ahead (4 or 8)
+};
 
 // Speculation: each step lists the kSpecK least-filled points whose trees are
 // not cached; their propagations run beside the fill, into a cache of
@@ -204,15 +217,17 @@ hipError_t launch_prep_batched(const GImgW *w_dev, const uint8_t *imgs_dev, cons
                                int B, int C, int wmode, hipStream_t st);
 
 // Propagations from sources (list or src_base + block) into K rows of out.
+// pfw: the sweeps' weight prefetch depth (0: 4; the autotuner may pick 8).
 hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st);
+                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw = 0);
 
 // Filling-rate method pieces for one image.
 hipError_t launch_fr_init(const FrState &fs, hipStream_t st);
 hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
 // One loop step: select + propagate + tree (one workgroup), then the fill.
 // If mid is given it is recorded between the two launches.
-hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid = nullptr);
+hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid = nullptr,
+                          const Tuning &tune = Tuning());
 
 // Batched naive: every (image, source) item in one launch.
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line,
@@ -233,8 +248,8 @@ inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }
 // Largest dynamic LDS a workgroup may use.
 constexpr size_t kMaxLds = 160 * 1024 - 1024;
 // The link fill needs 16-bit pixel ids and its tables in LDS.
-__host__ __device__ inline bool link_fill_fits(int N) {
-    return N >= 1 && N < (int)kNoId && link_fill_lds(N) <= kMaxLds;
+__host__ __device__ inline bool link_fill_fits(int N, int lanes = kFillLanes) {
+    return N >= 1 && N < (int)kNoId && link_fill_lds(N, lanes) <= kMaxLds;
 }
 
 }  // namespace gapd

@@ -47,10 +47,14 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
     fr_fill_block<kLds, kLdsCount>(fs, fs.packed, W, spk, red, blockIdx.x, gridDim.x);
 }
 
-// Fill variants of the speculative step: the link fill (kFillLinks, when its
-// tables fit LDS), the walk with a grandparent table (kFillA2) or the plain
-// walk with the tree words in LDS (kFillTree).
-constexpr int kFillTree = 0, kFillA2 = 1, kFillLinks = 2;
+// Fill variants of the speculative step: the link fill (when its tables fit
+// LDS) with 128 or 256 walking threads per block and 8 or 16 ancestor pairs
+// in flight per walk (the autotuner's choice), the walk with a grandparent
+// table (kFillA2) or the plain walk with the tree words in LDS (kFillTree).
+constexpr int kFillTree = 0, kFillA2 = 1, kFillLinks = 2;  // kFillLinks + (lanes == 256) + 2 * (pf == 8)
+constexpr int fill_links_variant(int lanes, int pf) { return kFillLinks + (lanes == 256 ? 1 : 0) + (pf == 8 ? 2 : 0); }
+constexpr int variant_lanes(int v) { return ((v - kFillLinks) & 1) ? 256 : 128; }
+constexpr int variant_pf(int v) { return ((v - kFillLinks) & 2) ? 8 : 16; }
 
 // The fill of the current step (blocks kSpecK..) beside the speculative
 // propagations of the candidates it listed (blocks 0..kSpecK-1, first, so
@@ -78,8 +82,9 @@ __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs
     }
     const int slot = fs.ctl->tree_slot;
     const uint32_t *tree = slot >= 0 ? slot_tree(fs, slot) : fs.packed;
-    if (kFill == kFillLinks) {
-        fill_links_block(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK);
+    if constexpr (kFill >= kFillLinks) {
+        fill_links_block<variant_lanes(kFill), variant_pf(kFill)>(fs, tree, g.W, (uint32_t *)smem, red,
+                                                                 blockIdx.x - kSpecK);
     } else {
         fr_fill_block<true, kLdsCount, kFill == kFillA2, kFill == kFillA2 ? 128 : 256>(
             fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK, gridDim.x - kSpecK);
@@ -122,7 +127,28 @@ struct FrStep {
         return hipGetLastError();
     }
 
-    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
+    template <bool kStageW>
+    static hipError_t launch_links(const GImg &g, int Wp, const FrState &fs, int max_rounds, hipStream_t st,
+                                   size_t lds, int lanes, int pf) {
+        const int blocks = (g.N + lanes - 1) / lanes;
+        switch (fill_links_variant(lanes, pf)) {
+            case fill_links_variant(256, 16):
+                return launch_fill_spec<kStageW, false, fill_links_variant(256, 16)>(g, Wp, fs, max_rounds, st, lds,
+                                                                                    blocks);
+            case fill_links_variant(128, 8):
+                return launch_fill_spec<kStageW, false, fill_links_variant(128, 8)>(g, Wp, fs, max_rounds, st, lds,
+                                                                                   blocks);
+            case fill_links_variant(256, 8):
+                return launch_fill_spec<kStageW, false, fill_links_variant(256, 8)>(g, Wp, fs, max_rounds, st, lds,
+                                                                                   blocks);
+            default:
+                return launch_fill_spec<kStageW, false, fill_links_variant(128, 16)>(g, Wp, fs, max_rounds, st, lds,
+                                                                                    blocks);
+        }
+    }
+
+    static hipError_t run(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid,
+                          const Tuning &tune) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         const size_t wbytes = (size_t)(CONN == 8 ? 4 : 2) * ((g.N + 1) / 2) * sizeof(uint32_t);
@@ -145,13 +171,14 @@ struct FrStep {
             const size_t sp = lds + (lds + wbytes <= kMaxLds ? wbytes : 0);
             const size_t a2 = pk + (size_t)g.N * 2;  // tree words + grandparents
             const int blocks2 = (g.N + kFillLanes - 1) / kFillLanes;
-            if (link_fill_fits(g.N)) {
-                const size_t ll = link_fill_lds(g.N);
+            const int lanes = tune.fill_lanes == 256 && link_fill_fits(g.N, 256) ? 256 : kFillLanes;
+            const int pf = tune.walk_pf == 8 ? 8 : 16;
+            if (link_fill_fits(g.N, lanes)) {
+                const size_t ll = std::max(sp, link_fill_lds(g.N, lanes));
                 if (lds + wbytes <= kMaxLds)
-                    e = launch_fill_spec<true, false, kFillLinks>(g, Wp, fs, max_rounds, st, std::max(sp, ll), blocks2);
+                    e = launch_links<true>(g, Wp, fs, max_rounds, st, ll, lanes, pf);
                 else
-                    e = launch_fill_spec<false, false, kFillLinks>(g, Wp, fs, max_rounds, st, std::max(sp, ll),
-                                                                   blocks2);
+                    e = launch_links<false>(g, Wp, fs, max_rounds, st, ll, lanes, pf);
             } else if (a2 <= kMaxLds && g.N < 0xFFFF) {
                 if (lds + wbytes <= kMaxLds)
                     e = launch_fill_spec<true, false, kFillA2>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
@@ -204,8 +231,8 @@ hipError_t GAPD_PART_CAT(fr_setup_part, GAPD_CONN, GAPD_S)(const GImg &g, const 
 }
 
 hipError_t GAPD_PART_CAT(fr_step_part, GAPD_CONN, GAPD_S)(const GImg &g, const FrState &fs, int max_rounds,
-                                                          hipStream_t st, hipEvent_t mid) {
-    return FrStep<GAPD_CONN, GAPD_S>::run(g, fs, max_rounds, st, mid);
+                                                          hipStream_t st, hipEvent_t mid, const Tuning &tune) {
+    return FrStep<GAPD_CONN, GAPD_S>::run(g, fs, max_rounds, st, mid, tune);
 }
 
 }  // namespace gapd

@@ -103,7 +103,7 @@ hipError_t launch_fr_init(const FrState &fs, hipStream_t st) {
 #define GAPD_FR_DECL(C, S)                                                                                   \
     hipError_t fr_setup_part_##C##_##S(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);   \
     hipError_t fr_step_part_##C##_##S(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st,     \
-                                      hipEvent_t mid);
+                                      hipEvent_t mid, const Tuning &tune);
 GAPD_FR_PARTS(GAPD_FR_DECL)
 
 hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st) {
@@ -114,10 +114,11 @@ hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hip
     return hipErrorInvalidValue;  // the tree methods need the distance field in LDS (sides <= 192)
 }
 
-hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid) {
+hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st, hipEvent_t mid,
+                          const Tuning &tune) {
     const int c = size_class(g.H > g.W ? g.H : g.W);
 #define GAPD_FR_STEP_CASE(C, S) \
-    if (g.conn == C && c == S) return fr_step_part_##C##_##S(g, fs, max_rounds, st, mid);
+    if (g.conn == C && c == S) return fr_step_part_##C##_##S(g, fs, max_rounds, st, mid, tune);
     GAPD_FR_PARTS(GAPD_FR_STEP_CASE)
     return hipErrorInvalidValue;
 }

@@ -12,8 +12,9 @@ namespace {
 // src_list[b] (or src_base + b) and writes row b of out (Section 1).
 // With kGlobal the distance field lives in the output row itself (images too
 // large for LDS); otherwise in LDS, and the row is written once at the end.
+// PFW: the sweeps' weight prefetch depth (0: the default of 4 lines).
 // ---------------------------------------------------------------------------------------------
-template <int CONN, int S, bool kGlobal>
+template <int CONN, int S, bool kGlobal, int PFW = 0>
 __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, const int32_t *src_list,
                                                               int src_base, int32_t *out, int max_rounds,
                                                               FrCtl *ctl) {
@@ -26,7 +27,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wd + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, S, kGlobal>(g, d, Wd, max_rounds);
+    const int r = relax_block<CONN, S, kGlobal, false, PFW>(g, d, Wd, max_rounds);
     if (threadIdx.x == 0) {
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
@@ -72,11 +73,14 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
 template <int CONN, int S>
 struct RelaxRows {
     static hipError_t run(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                          int max_rounds, FrCtl *ctl, hipStream_t st) {
+                          int max_rounds, FrCtl *ctl, hipStream_t st, int pfw) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         if (lds <= kMaxLds) {
             auto k = k_relax_rows<CONN, S, false>;
+            if constexpr (S <= 128) {  // the deeper weight ring where a lane holds at most two elements
+                if (pfw == 8) k = k_relax_rows<CONN, S, false, 8>;
+            }
             hipError_t e = set_lds(k, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k, dim3(K), dim3(kRelaxThreads), lds, st, g, Wp, src_list, src_base, out,
@@ -108,10 +112,10 @@ struct RelaxRowsBatched {
 
 // ---- launchers ----------------------------------------------------------------------------------
 hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st) {
+                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw) {
     if (K <= 0) return hipSuccess;
     return dispatch<RelaxRows>(g.conn, g.H > g.W ? g.H : g.W, g, src_list, src_base, K, out, max_rounds, ctl,
-                               st);
+                               st, pfw);
 }
 
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line, size_t lds_bytes,

@@ -24,7 +24,7 @@ JOB_ALL_PAIRS, JOB_MULTI_SOURCE = 0, 1
 
 EXPORTED = [
     "gapd_create", "gapd_set_stream", "gapd_workspace_size", "gapd_set_workspace", "gapd_sssp",
-    "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_all_pairs_noalloc", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
+    "gapd_all_pairs", "gapd_all_pairs_spiral", "gapd_all_pairs_noalloc", "gapd_autotune", "gapd_set_tuning", "gapd_destroy", "gapd_strerror", "gapd_last_error", "gapd_batched_workspace_size",
     "gapd_all_pairs_batched", "gapd_server_create", "gapd_serve_submit", "gapd_serve_poll", "gapd_serve_wait",
     "gapd_serve_release", "gapd_server_destroy", "gapd_graph_create", "gapd_graph_set_stream",
     "gapd_graph_workspace_size", "gapd_graph_set_workspace", "gapd_graph_sssp", "gapd_graph_all_pairs",
@@ -47,6 +47,12 @@ class Stats(ctypes.Structure):
                 ("ms_fill_kernels", ctypes.c_float), ("graph_replays", ctypes.c_int32),
                 ("n_prop_speculative", ctypes.c_int64), ("n_cache_hits", ctypes.c_int64),
                 ("step_trace", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fill_lanes", ctypes.c_int32), ("walk_pf", ctypes.c_int32), ("spec_cap", ctypes.c_int32),
+                ("naive_pfw", ctypes.c_int32), ("ms", ctypes.c_float), ("ms_default", ctypes.c_float),
+                ("candidates", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -86,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "gapd_last_error": ([P], ctypes.c_char_p),
         "gapd_batched_workspace_size": ([P, P, I, I, I, I, ctypes.POINTER(SZ)], I),
         "gapd_all_pairs_noalloc": ([P, I, P, ctypes.POINTER(Stats)], I),
+        "gapd_autotune": ([P, I, P, ctypes.POINTER(Tuning)], I),
+        "gapd_set_tuning": ([P, I, ctypes.POINTER(Tuning)], I),
         "gapd_all_pairs_batched": ([P, P, P, I, I, I, I, I, P, P, P, P, P, SZ, P], I),
         "gapd_server_create": ([P, SZ, I, ctypes.POINTER(P)], I),
         "gapd_serve_submit": ([P, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)], I),
@@ -227,6 +235,22 @@ class Context:
         st.time_kernels = 1 if time_kernels else 0
         _check(load_library().gapd_all_pairs(self._h, mode, _dptr(out), ctypes.byref(st)), self._h)
         return out, _stats(st)
+
+    def autotune(self, mode: int, out=None) -> dict:
+        """gapd_autotune: time the candidate launch shapes of `mode` on this image
+        and keep the fastest (JSON cache); returns the choice and both timings."""
+        import torch
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.int32, device="cuda")
+        self._ensure_workspace(mode)
+        t = Tuning()
+        _check(load_library().gapd_autotune(self._h, mode, _dptr(out), ctypes.byref(t)), self._h)
+        return {k: getattr(t, k) for k, _ in Tuning._fields_ if not k.startswith("_")}
+
+    def set_tuning(self, mode: int, fill_lanes=128, walk_pf=16, spec_cap=32, naive_pfw=4) -> None:
+        """gapd_set_tuning: pin the launch shapes of `mode` on images of this key."""
+        t = Tuning(fill_lanes, walk_pf, spec_cap, naive_pfw, 0.0, 0.0, 0, 0)
+        _check(load_library().gapd_set_tuning(self._h, mode, ctypes.byref(t)), self._h)
 
     def all_pairs_noalloc(self, mode: int, out, sources_out=None, filled_out=None):
         """gapd_all_pairs_noalloc: the library allocates nothing (the tree modes use
