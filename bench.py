@@ -212,22 +212,51 @@ def fill_trace(ctx, mode, out, path=None):
     return summary
 
 
-def measured_traffic(workload, kernel_prefix):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by the plain-copy calibration),
-    or None when there is none or the kernels have changed since it was taken."""
+def _counters(workload, kernel_prefix):
+    """The committed rocprofv3 counter summary of a kernel (profiles/
+    traffic_<workload>.json), or None when there is none or the kernels have
+    changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernels_sha256") != kernels_sha256():
-        return None
+        return None, None
     for name, k in t["kernels"].items():
         if name.startswith(kernel_prefix):
-            kib = k["fetch_kib"] * t["fetch_factor"] + k["write_kib"] * t["write_factor"]
-            return round(kib * 1024 / max(k["dispatches"], 1))
-    return None
+            return t, k
+    return None, None
+
+
+def measured_traffic(workload, kernel_prefix):
+    """HBM bytes per launch of a kernel from the counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by the plain-copy calibration), or None."""
+    t, k = _counters(workload, kernel_prefix)
+    if k is None or "fetch_kib" not in k:
+        return None
+    kib = k["fetch_kib"] * t["fetch_factor"] + k["write_kib"] * t["write_factor"]
+    return round(kib * 1024 / max(k["dispatches"], 1))
+
+
+def alu_side(ops_per_launch, ms, workload, kernel_prefix):
+    """The ALU side of a kernel's roofline: the method's integer operations
+    per launch (2 per relaxation: add and min) over the live launch duration,
+    against the chip's int32 vector peak; beside it the issued VALU lane
+    operations (SQ_INSTS_VALU x 64 per launch, from the counter summary of
+    the same kernels) over the same duration, when there is one."""
+    ach = ops_per_launch / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    d = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
+         "frac": round(ach / VALU_PEAK_TOPS, 6), "ops_per_launch": round(ops_per_launch)}
+    _, k = _counters(workload, kernel_prefix)
+    if k is not None and "valu_insts" in k and ms > 0:
+        lane_ops = 64.0 * k["valu_insts"] / max(k["dispatches"], 1)
+        iss = lane_ops / (ms * 1e-3) / 1e12
+        d.update(issued_lane_ops_per_launch=round(lane_ops), issued_achieved=round(iss, 4),
+                 issued_frac=round(iss / VALU_PEAK_TOPS, 6))
+    else:
+        d.update(issued_lane_ops_per_launch=None, issued_achieved=None, issued_frac=None)
+    return d
 
 
 def single_image_line(args, workload, img, conn, desc, fr=True):
@@ -248,6 +277,8 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
     roof_naive["kernel"] = "k_relax_rows (one propagation per workgroup, writes its row of D)"
     roof_naive["algorithmic_bytes_per_launch"] = 4 * N * N
     roof_naive["traffic"] = measured_traffic(workload, "k_relax_rows<")
+    naive_rounds_total = float(np.mean([s.rounds for s in nst]))
+    roof_naive["alu"] = alu_side(2.0 * E_dir * naive_rounds_total, naive_kernel_ms, workload, "k_relax_rows<")
     line = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
             "data": "synthetic", "config": dict(desc, workload=workload, N=N, conn=conn,
@@ -269,15 +300,22 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
     # loop misses, speculative)
     rounds = s0.rounds / max(n_prop - hits + n_spec + 2, 1)
     # Per-launch algorithmic work:
-    #   fill: the D entries and mask bits the whole run writes once, averaged per launch;
-    #   step: |E_dir| x rounds relaxations (add + min) of one propagation.
-    fill_bytes = (4.0 * N * N + N * N / 8.0) / max(n_prop, 1)
+    #   fill: the D entries and mask bits the whole run writes once, averaged
+    #   per launch, plus one propagation's distances and predecessors (4N + N
+    #   bytes: the tree the launch reads);
+    #   ALU: 2 ops (add, min) per relaxation, |E_dir| relaxations per sweep
+    #   round; the fill launch holds the speculative pieces' rounds, the step
+    #   launch the rest (cache misses; the two setup propagations included).
+    fill_bytes = (4.0 * N * N + N * N / 8.0) / max(n_prop, 1) + 5.0 * N
     roof_fill = roofline_hbm(fill_bytes, fill_ms)
     fill_name = "k_fr_fill_spec" if spec else "k_fr_fill"
     roof_fill.update(kernel=fill_name + " (redundancy fill along the geodesic tree"
                      + (", beside the speculative propagations)" if spec else ")"),
                      algorithmic_bytes_per_launch=round(fill_bytes), avg_launch_ms=round(fill_ms, 5),
                      traffic=measured_traffic(workload, fill_name + "<"))
+    spec_rounds = int(getattr(s0, "rounds_speculative", 0))
+    roof_fill["alu"] = alu_side(2.0 * E_dir * spec_rounds / max(n_prop, 1), fill_ms, workload, fill_name + "<")
+    step_ops = 2.0 * E_dir * (s0.rounds - spec_rounds) / max(n_prop, 1)
     if spec:
         # With the tree cache a step launch is the select pass (count, rank or
         # distance, and cache slot: 12 bytes per point read) plus, on a miss,
@@ -288,8 +326,8 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
                                 "tree on a cache miss; one workgroup)",
                          algorithmic_bytes_per_launch=round(step_bytes), avg_launch_ms=round(step_ms, 5),
                          traffic=measured_traffic(workload, "k_fr_step_spec<"))
+        roof_step["alu"] = alu_side(step_ops, step_ms, workload, "k_fr_step_spec<")
     else:
-        step_ops = 2.0 * E_dir * rounds
         ach = step_ops / (step_ms * 1e-3) / 1e12
         roof_step = {"bound": "alu", "achieved": round(ach, 4), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
                      "frac": round(ach / VALU_PEAK_TOPS, 6), "traffic": measured_traffic(workload, "k_fr_step<"),
@@ -302,6 +340,7 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
                 n_prop=int(n_prop), n_prop_setup=int(s0.n_prop_setup),
                 n_prop_speculative=n_spec, n_cache_hits=hits,
                 cache_hit_rate=round(hits / max(n_prop - 1, 1), 4),
+                rounds_per_propagation=round(rounds, 2), rounds_speculative=spec_rounds,
                 propagation_saving_vs_naive=round(1.0 - (n_prop + s0.n_prop_setup) / N, 4),
                 fr_setup_ms=round(float(np.mean([s.ms_setup for s in fst])), 3),
                 fr_loop_kernel_ms={"select_propagate": round(step_ms * n_prop, 3),
@@ -366,46 +405,100 @@ def batched_line(args):
             "propagation_saving_vs_naive": round(1.0 - (float(np.sum(fprop)) + 2 * len(imgs)) / n_sum, 4),
             "roofline": roofline_hbm(4.0 * total, float(np.mean(nms)))}
     line["roofline"]["kernel"] = "k_relax_rows_batched (whole naive call, output bytes only)"
+    # ALU side: the sweep rounds of every image's propagations, counted by a
+    # single-image naive call per image (outside the timed calls; the batched
+    # kernel runs the same sweeps to the same fixed points)
+    ops = 0.0
+    for im in imgs:
+        _, st = gapd.Context(im).all_pairs(gapd.MODE_NAIVE)
+        ops += 2.0 * edges_directed(im.shape[0], im.shape[1], 4) * st.rounds
+    torch.cuda.synchronize()
+    line["roofline"]["alu"] = alu_side(ops, float(np.mean(nms)), "batched256", "k_relax_rows_batched<")
     return line
 
 
-def serve_line(args):
+def serve_line(args, rate=None):
+    """C5: Poisson arrivals of a 70/30 mix of all-pairs blob jobs (sides 64..192)
+    and multi-source jobs on resident 512x512 blob images (K in 1..512), through
+    the server.  Latency runs from each request's scheduled arrival time to its
+    completion, so it includes queueing."""
     import torch
     import synth
     from paper_2007_16076_amd import gapd
-    rate, n = args.rate, args.requests
+    rate = args.rate if rate is None else rate
+    n = args.requests
     reqs, images = synth.serving_trace(rate, n, side=(64, 192))
     free, _ = torch.cuda.mem_get_info()
     arena_bytes = int(min(200e9, free * 0.8))
     srv = gapd.Server(arena_bytes, max_slots=args.slots)
     mode = gapd.MODE_TREE_FILL_FR if args.serve_mode == "tree_fill" else gapd.MODE_NAIVE
     torch.cuda.synchronize()
+    # A collector thread releases every finished job at once (its result then
+    # leaves the arena), as a client that consumes results would; ctypes
+    # drops the GIL inside the library calls.
+    import queue
+    import threading
+    pending_q = queue.Queue()
+    lat, lat_kind, counts = [], {"all_pairs": [], "multi_source": []}, {"entries": 0, "done": 0}
+
+    def collect():
+        pending, last_log = [], time.perf_counter()
+        while counts["done"] < n:
+            while True:
+                try:
+                    pending.append(pending_q.get_nowait())
+                except queue.Empty:
+                    break
+            still = []
+            for t, r, lag in pending:
+                res = srv.poll(t)
+                if res is None:
+                    still.append((t, r, lag))
+                    continue
+                ms = (res.t_done - res.t_submit + lag) * 1e3
+                lat.append(ms)
+                lat_kind[r.kind].append(ms)
+                counts["entries"] += res.elems
+                srv.release(t)
+                counts["done"] += 1
+            pending = still
+            if time.perf_counter() - last_log > 20:
+                log(f"[serve {args.serve_mode} rate {rate}] {counts['done']}/{n} done")
+                last_log = time.perf_counter()
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=collect, daemon=True)
     t0 = time.perf_counter()
-    tickets = []
+    th.start()
     for r in reqs:
-        while time.perf_counter() - t0 < r.t_arrival:
-            time.sleep(min(0.001, r.t_arrival - (time.perf_counter() - t0)))
+        while True:
+            wait_s = r.t_arrival - (time.perf_counter() - t0)
+            if wait_s <= 0:
+                break
+            time.sleep(min(0.001, wait_s))
+        lag = time.perf_counter() - t0 - r.t_arrival  # submitted this late after its scheduled arrival
         if r.kind == "all_pairs":
             t = srv.submit_all_pairs(images[r.image_id], mode=mode)
         else:
             t = srv.submit_multi_source(images[r.image_id], r.sources)
-        tickets.append((t, r))
-    lat, entries, done = [], 0, 0
-    for t, r in tickets:
-        res = srv.wait(t)
-        lat.append((res.t_done - res.t_submit) * 1e3)
-        entries += res.elems
-        srv.release(t)
-        done += 1
+        pending_q.put((t, r, lag))
+    th.join()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    entries = counts["entries"]
     srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    kinds = {k: {"jobs": len(v), "p50_ms": round(pct(v, 50), 2), "p99_ms": round(pct(v, 99), 2)}
+             for k, v in lat_kind.items() if v}
+    log(f"[serve {args.serve_mode} rate {rate}] {n} jobs in {wall:.1f} s")
     return {"metric": METRIC, "value": entries / wall, "unit": "distance entries/s", "n_gpus": 1,
             "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1), "p50_ms": round(pct(lat, 50), 2),
-            "p99_ms": round(pct(lat, 99), 2), "jobs_per_s": round(n / wall, 2), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "p99_ms": round(pct(lat, 99), 2), "jobs_per_s": round(n / wall, 2), "by_kind": kinds,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
             "config": {"workload": "serve", "rate_req_s": rate, "requests": n, "slots": args.slots,
-                       "all_pairs_mode": args.serve_mode, "arena_bytes": arena_bytes}}
+                       "all_pairs_mode": args.serve_mode, "arena_bytes": arena_bytes,
+                       "latency": "from the scheduled arrival to completion"}}
 
 
 def hbmcopy_line(args):
@@ -565,6 +658,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of each oracle timing sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=30.0)
+    ap.add_argument("--rates", default=None, metavar="R1,R2,...",
+                    help="serve: sweep these arrival rates (req/s), one JSON line each")
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--serve-mode", default="naive", choices=["naive", "tree_fill"])
@@ -616,6 +711,10 @@ def main():
         line = batched_line(args)
     elif args.workload == "hbmcopy":
         line = hbmcopy_line(args)
+    elif args.rates:
+        for r in [float(x) for x in args.rates.split(",")]:
+            print(json.dumps(serve_line(args, r)), flush=True)
+        return
     else:
         line = serve_line(args)
     print(json.dumps(line), flush=True)

@@ -114,6 +114,8 @@ typedef struct {
                                constant clock,
                                hipDeviceAttributeWallClockRate kHz).  Tracing adds a
                                little work to those kernels.                             */
+    int64_t  rounds_speculative; /* filling-rate and extrema modes: the sweep rounds of the
+                                    speculative propagations (part of rounds)             */
 } gapd_stats;
 
 /* ---- single image ------------------------------------------------------------------------ */

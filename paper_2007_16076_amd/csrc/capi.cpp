@@ -252,6 +252,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    s.rounds_speculative = 0;
     s.graph_replays = 0;
     int st = GAPD_OK;
     hipEvent_t e0, e1, e2;
@@ -300,6 +301,7 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
         s.rounds = hc.rounds;
         s.n_prop_speculative = hc.spec_props;
         s.n_cache_hits = hc.spec_hits;
+        s.rounds_speculative = hc.spec_rounds;
         if (rule != kRuleSpiral) {
             s.n_prop_setup = 2;
             s.centroid = hc.centroid;
@@ -465,6 +467,7 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    s.rounds_speculative = 0;
     s.graph_replays = 0;
     if (mode == GAPD_MODE_NAIVE) {
         // no scratch: the naive method only needs the context's control block
@@ -501,6 +504,7 @@ int gapd_all_pairs_noalloc(gapd_ctx *ctx, int mode, int32_t *out, gapd_stats *st
     s.rounds = hc.rounds;
     s.n_prop_speculative = hc.spec_props;
     s.n_cache_hits = hc.spec_hits;
+    s.rounds_speculative = hc.spec_rounds;
     s.n_prop_setup = 2;
     s.centroid = hc.centroid;
     return st;

@@ -1574,7 +1574,10 @@ __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem
             tree[v] = (uint32_t)d[y * Wp + x];
         }
     }
-    if (threadIdx.x == 0) atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
+        atomicAdd((unsigned long long *)&ctl->spec_rounds, 1ull);
+    }
     return r;
 }
 

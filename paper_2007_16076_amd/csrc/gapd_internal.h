@@ -68,6 +68,7 @@ struct FrCtl {
     int32_t sp_turn1;   // spiral rules: current turn + 1 (0: none yet)
     int32_t _pad;
     int64_t spec_props; // speculative propagations computed
+    int64_t spec_rounds;  // sweep rounds of the speculative pieces (also counted in rounds)
 };
 
 // Device state of the filling-rate method for one image.

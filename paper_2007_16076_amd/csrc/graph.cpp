@@ -282,6 +282,7 @@ int gapd_graph_all_pairs(gapd_graph *G, int mode, int32_t *out, gapd_stats *stp)
     gapd_stats &s = stp ? *stp : local;
     s.n_prop = 0; s.n_prop_setup = 0; s.rounds = 0; s.centroid = -1; s.ms_total = 0; s.ms_setup = 0;
     s.ms_kernel = 0; s.ms_step_kernels = 0; s.ms_fill_kernels = 0; s.n_prop_speculative = 0; s.n_cache_hits = 0;
+    s.rounds_speculative = 0;
     s.graph_replays = 0;
     hipEvent_t e0, e1, e2;
     GHIP_OR_FAIL(G, hipEventCreate(&e0));

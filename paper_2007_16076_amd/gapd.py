@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
                 ("time_kernels", ctypes.c_int32), ("ms_step_kernels", ctypes.c_float),
                 ("ms_fill_kernels", ctypes.c_float), ("graph_replays", ctypes.c_int32),
                 ("n_prop_speculative", ctypes.c_int64), ("n_cache_hits", ctypes.c_int64),
-                ("step_trace", ctypes.c_void_p)]
+                ("step_trace", ctypes.c_void_p), ("rounds_speculative", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -163,6 +163,7 @@ class AllPairsStats:
     n_prop_speculative: int = 0
     n_cache_hits: int = 0
     graph_replays: int = 0
+    rounds_speculative: int = 0
 
 
 class Context:
@@ -286,7 +287,7 @@ class Context:
 def _stats(st) -> "AllPairsStats":
     return AllPairsStats(st.n_prop, st.n_prop_setup, st.rounds, st.centroid, st.ms_total, st.ms_setup,
                          st.ms_kernel, st.ms_step_kernels, st.ms_fill_kernels, st.n_prop_speculative,
-                         st.n_cache_hits, st.graph_replays)
+                         st.n_cache_hits, st.graph_replays, st.rounds_speculative)
 
 
 def batched_workspace_size(shapes, C: int = 1, conn: int = CONN4, mode: int = MODE_NAIVE) -> int:
