@@ -181,10 +181,10 @@ def fill_trace(ctx, mode, out, path=None):
     summary by phase of the run; the per-step table goes to ``path``."""
     import torch
     N = ctx.N
-    tr = torch.zeros(16 * N, dtype=torch.int64, device="cuda")
+    tr = torch.zeros(24 * N, dtype=torch.int64, device="cuda")
     _, st = ctx.all_pairs(mode, out=out, step_trace=tr)
     torch.cuda.synchronize()
-    t = tr.view(N, 16)[: st.n_prop].cpu().numpy().astype(np.float64)
+    t = tr.view(N, 24)[: st.n_prop].cpu().numpy().astype(np.float64)
     us = 1e3 / wall_clock_khz()
     start = (2.0 ** 63 - 1) - t[:, 6]
     span = np.where(t[:, 11] > 0, (t[:, 7] - start) * us, 0.0)
@@ -196,6 +196,11 @@ def fill_trace(ctx, mode, out, path=None):
             "launch_span_us": launch_span,
             "spec_tail_us": np.where(t[:, 8] > 0, np.maximum(t[:, 13] - t[:, 7], 0.0) * us, 0.0),
             "cache_hit": t[:, 14]}
+    nb = np.maximum(t[:, 11], 1)
+    for i, k in enumerate(["tables", "detect", "write", "flush"]):
+        cols[f"ph_{k}_us"] = t[:, 16 + i] * us / nb  # mean over the step's fill blocks
+    cols["ph_detect_max_us"] = t[:, 22] * us
+    cols["ph_write_max_us"] = t[:, 23] * us
     n = st.n_prop
     edges = sorted({0, min(100, n), min(1000, n), min(3000, n), min(6000, n), min(9000, n), n})
     phases = []

@@ -101,17 +101,20 @@ typedef struct {
                                     likely next sources (not counted in n_prop)          */
     int64_t  n_cache_hits;  /* filling-rate steps whose propagation was such a tree, taken
                                from the cache instead of being propagated again          */
-    int64_t *step_trace;    /* input: nullable DEVICE buffer of 16*N int64, zeroed by the
+    int64_t *step_trace;    /* input: nullable DEVICE buffer of 24*N int64, zeroed by the
                                call; for the filling-rate and extrema modes with the tree
-                               cache, loop step t fills entries 16t..16t+15 with the
+                               cache, loop step t fills entries 24t..24t+23 with the
                                ancestors the fill walked, the new pairs, the longest walk,
                                the pixels that walked, the slowest fill block, the sum over
                                fill blocks, 2^63-1 minus the first block start, the last
                                block end, the speculative pieces run, the slowest piece,
                                the select kernel, the fill blocks, the pieces that reached
                                their fixed point, the last piece end, 1 if the step's tree
-                               came from the cache, and 0 (times in ticks of the device's
-                               constant clock,
+                               came from the cache, 0, then the link fill's phases summed
+                               over its workgroups (link tables built, loads-only walks,
+                               writing walks, counters flushed), 0, 0, and the slowest
+                               workgroup's two walk phases
+                               (times in ticks of the device's constant clock,
                                hipDeviceAttributeWallClockRate kHz).  Tracing adds a
                                little work to those kernels.                             */
     int64_t  rounds_speculative; /* filling-rate and extrema modes: the sweep rounds of the
@@ -205,7 +208,8 @@ typedef struct {
     float   ms;           /* the chosen shapes' call time                                  */
     float   ms_default;   /* the default shapes' call time                                 */
     int32_t candidates;   /* shapes timed                                                   */
-    int32_t _pad;
+    int32_t naive_check1; /* naive mode: check the edges after the first sweep round (1)
+                             or only after the second (0)                              */
 } gapd_tuning;
 
 /* Time the candidate launch shapes of `mode` (GAPD_MODE_NAIVE,
@@ -221,9 +225,10 @@ typedef struct {
 int gapd_autotune(gapd_ctx *ctx, int mode, int32_t *out, gapd_tuning *best);
 
 /* Pin the launch shapes that `mode` uses on images of this context's key,
- * for the rest of the process (the cache file is not written).  Only the
- * first four fields of t are read; values outside fill_lanes {128, 256},
- * walk_pf {8, 16}, spec_cap 1..32, naive_pfw {4, 8} give GAPD_EINVAL. */
+ * for the rest of the process (the cache file is not written).  Only
+ * fill_lanes, walk_pf, spec_cap, naive_pfw and naive_check1 are read; values
+ * outside fill_lanes {128, 256}, walk_pf {8, 16}, spec_cap 1..32, naive_pfw
+ * {4, 8}, naive_check1 {0, 1} give GAPD_EINVAL. */
 int gapd_set_tuning(gapd_ctx *ctx, int mode, const gapd_tuning *t);
 
 /* Release the context and its device memory (not the caller's buffers). */

@@ -266,7 +266,8 @@ int all_pairs_impl(gapd_ctx *ctx, int rule, int h, const uint32_t *draws, int32_
     HIP_OR_FAIL(ctx, hipEventRecord(e0, ctx->stream));
     if (rule < 0) {
         st = run_rows(ctx->g, nullptr, 0, ctx->N, out, ctx->max_rounds, ctx->ctl, ctx->stream, ctx->err,
-                      ctx->poisoned, &s.rounds, &s.ms_kernel, tune.naive_pfw);
+                      ctx->poisoned, &s.rounds, &s.ms_kernel, tune.naive_pfw,
+                      tune.naive_check1);
         HIP_OR_FAIL(ctx, hipEventRecord(e2, ctx->stream));
         HIP_OR_FAIL(ctx, hipEventSynchronize(e2));
         s.n_prop = ctx->N;
@@ -338,11 +339,13 @@ int gapd_autotune(gapd_ctx *ctx, int mode, int32_t *out, gapd_tuning *best) {
     // The candidates, the defaults first.
     std::vector<Tuning> cands;
     if (mode == GAPD_MODE_NAIVE) {
-        for (int pfw : {4, 8}) {
-            Tuning t;
-            t.naive_pfw = pfw;
-            cands.push_back(t);
-        }
+        for (int c1 : {kNaiveCheck1, 1 - kNaiveCheck1})
+            for (int pfw : {4, 8}) {
+                Tuning t;
+                t.naive_pfw = pfw;
+                t.naive_check1 = c1;
+                cands.push_back(t);
+            }
     } else {
         for (int lanes : {kFillLanes, 256})
             for (int pf : {16, 8})
@@ -375,10 +378,10 @@ int gapd_autotune(gapd_ctx *ctx, int mode, int32_t *out, gapd_tuning *best) {
         best->walk_pf = cands[bi].walk_pf;
         best->spec_cap = cands[bi].spec_cap;
         best->naive_pfw = cands[bi].naive_pfw;
+        best->naive_check1 = cands[bi].naive_check1;
         best->ms = best_ms;
         best->ms_default = default_ms;
         best->candidates = (int32_t)cands.size();
-        best->_pad = 0;
     }
     return GAPD_OK;
 }
@@ -390,14 +393,16 @@ int gapd_set_tuning(gapd_ctx *ctx, int mode, const gapd_tuning *t) {
     if (mode != GAPD_MODE_NAIVE && mode != GAPD_MODE_TREE_FILL_FR && mode != GAPD_MODE_TREE_FILL_EXTREMA)
         return fail(ctx, GAPD_EINVAL, "only the naive, filling-rate and extrema modes are tuned");
     if ((t->fill_lanes != 128 && t->fill_lanes != 256) || (t->walk_pf != 8 && t->walk_pf != 16) ||
-        t->spec_cap < 1 || t->spec_cap > kSpecK || (t->naive_pfw != 4 && t->naive_pfw != 8))
+        t->spec_cap < 1 || t->spec_cap > kSpecK || (t->naive_pfw != 4 && t->naive_pfw != 8) ||
+        (t->naive_check1 != 0 && t->naive_check1 != 1))
         return fail(ctx, GAPD_EINVAL, "unsupported launch shapes (fill_lanes 128|256, walk_pf 8|16, spec_cap 1..32, "
-                                      "naive_pfw 4|8)");
+                                      "naive_pfw 4|8, naive_check1 0|1)");
     Tuning x;
     x.fill_lanes = t->fill_lanes;
     x.walk_pf = t->walk_pf;
     x.spec_cap = t->spec_cap;
     x.naive_pfw = t->naive_pfw;
+    x.naive_check1 = t->naive_check1;
     store_tuning(tune_key(ctx->H, ctx->W, ctx->C, ctx->conn, mode), x, 0.0, false);
     return GAPD_OK;
 }
@@ -524,7 +529,8 @@ void gapd_destroy(gapd_ctx *ctx) {
 namespace gapd {
 
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
-             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel, int pfw) {
+             hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out, float *ms_kernel, int pfw,
+             int check1) {
     // Launch errors are read with hipGetLastError: drop one that an earlier,
     // unrelated call left pending so it is not taken for ours.
     (void)hipGetLastError();
@@ -534,7 +540,7 @@ int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_
     }
     hipError_t e = hipMemsetAsync(ctl, 0, sizeof(FrCtl), stream);
     if (e == hipSuccess && ms_kernel) e = hipEventRecord(k0, stream);
-    if (e == hipSuccess) e = launch_relax_rows(g, src_list, src_base, K, out, max_rounds, ctl, stream, pfw);
+    if (e == hipSuccess) e = launch_relax_rows(g, src_list, src_base, K, out, max_rounds, ctl, stream, pfw, check1);
     if (e == hipSuccess && ms_kernel) e = hipEventRecord(k1, stream);
     FrCtl hc{};
     if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl, sizeof(FrCtl), hipMemcpyDeviceToHost, stream);

@@ -34,10 +34,11 @@ constexpr int kTreeMaxSide = 192;
 inline bool tree_methods_fit(int H, int W) { return H <= kTreeMaxSide && W <= kTreeMaxSide; }
 
 // Propagations from K sources into K rows of out; synchronises the stream.
-// pfw: the sweeps' weight prefetch depth (0: default).
+// pfw: the sweeps' weight prefetch depth (0: default); check1: check the
+// edges after the first round already.
 int run_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out, int max_rounds, FrCtl *ctl,
              hipStream_t stream, std::string &err, bool &poisoned, int64_t *rounds_out = nullptr,
-             float *ms_kernel = nullptr, int pfw = 0);
+             float *ms_kernel = nullptr, int pfw = 0, int check1 = kNaiveCheck1);
 
 // Autotuned launch shapes (tune.cpp): the cache key of an image and method,
 // and the cached shapes for it (defaults when the cache has none).

@@ -44,7 +44,8 @@ __host__ __device__ inline uint32_t tw_code(uint32_t w) { return w & 15u; }
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Tree-cache slot sl: its tree words, or while running its partial distance field.
-__device__ __forceinline__ uint32_t *slot_tree(const FrState &fs, int sl) { return fs.cache + (size_t)sl * fs.N; }
+// Slots are al4w(N) words apart, so every tree starts 16-byte aligned.
+__device__ __forceinline__ uint32_t *slot_tree(const FrState &fs, int sl) { return fs.cache + (size_t)sl * al4w(fs.N); }
 
 // Constant-clock timestamp (100 MHz) for the optional per-step trace.
 __device__ __forceinline__ int64_t trace_clock() { return (int64_t)wall_clock64(); }
@@ -111,22 +112,27 @@ __device__ __forceinline__ int ldd(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Block-wide copy of n words from global memory into LDS: 16-byte loads,
-// several in flight per thread before any is stored.
-__device__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
-    constexpr int U = 8;
+// Block-wide copy of n words from global memory into LDS: 16-byte loads, U
+// in flight per thread before any is stored.  The stores take the same
+// clamped index as the loads, so lanes past the end rewrite the last element
+// with its own value: no branch, which keeps the compiler from moving each
+// load next to its store (and waiting for it there).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <int U = 8>
+__device__ __forceinline__ void copy_to_lds(uint32_t *dst, const uint32_t *src, int n) {
+    typedef const __attribute__((address_space(1))) u32x4 *gptr4;  // global memory: plain vector loads
     const int n4 = n / 4;
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-    for (int base = threadIdx.x; base < n4; base += blockDim.x * U) {
-        uint4 t[U];
+    const gptr4 s4 = (gptr4)src;
+    u32x4 *d4 = reinterpret_cast<u32x4 *>(dst);
+    const int nb = (int)blockDim.x;
+    for (int base = threadIdx.x; base < n4; base += nb * U) {
+        u32x4 t[U];
 #pragma unroll
-        for (int k = 0; k < U; ++k) t[k] = s4[min(base + k * (int)blockDim.x, n4 - 1)];
+        for (int k = 0; k < U; ++k) t[k] = s4[min(base + k * nb, n4 - 1)];
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (base + k * (int)blockDim.x < n4) d4[base + k * blockDim.x] = t[k];
+        for (int k = 0; k < U; ++k) d4[min(base + k * nb, n4 - 1)] = t[k];
     }
-    for (int i = n4 * 4 + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    for (int i = n4 * 4 + threadIdx.x; i < n; i += nb) dst[i] = src[i];
 }
 
 template <int CTRL>
@@ -322,8 +328,14 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
 // Neighbour k of pixel (y, x), in ascending pixel-index order:
 // 0:(-1,-1) 1:(-1,0) 2:(-1,+1) 3:(0,-1) 4:(0,+1) 5:(+1,-1) 6:(+1,0) 7:(+1,+1).
 // The 4-neighbourhood uses codes 1, 3, 4, 6.
-__device__ __forceinline__ int code_dy(int k) { return k < 3 ? -1 : (k < 5 ? 0 : 1); }
-__device__ __forceinline__ int code_dx(int k) { return k < 3 ? k - 1 : (k == 3 ? -1 : (k == 4 ? 1 : k - 6)); }
+// Decoded without branches: 2 bits per code hold dy + 1 and dx + 1; the root
+// code (15) decodes to (0, 0), so its "parent" offset is 0.
+constexpr uint32_t kCodeDy1 = 0u | 0u << 2 | 0u << 4 | 1u << 6 | 1u << 8 | 2u << 10 | 2u << 12 | 2u << 14 | 1u << 30;
+constexpr uint32_t kCodeDx1 = 0u | 1u << 2 | 2u << 4 | 0u << 6 | 2u << 8 | 0u << 10 | 1u << 12 | 2u << 14 | 1u << 30;
+__device__ __forceinline__ int code_dy(int k) { return (int)((kCodeDy1 >> (2 * k)) & 3u) - 1; }
+__device__ __forceinline__ int code_dx(int k) { return (int)((kCodeDx1 >> (2 * k)) & 3u) - 1; }
+// Pixel-index offset of neighbour k in an image of width W (< 2^23).
+__device__ __forceinline__ int code_off(int k, int W) { return __mul24(code_dy(k), W) + code_dx(k); }
 
 template <int CONN>
 __device__ __forceinline__ bool code_used(int k) {
@@ -732,7 +744,7 @@ __device__ __forceinline__ int turn_pixel(const Turn &t, int W, int p) {
 // member floor(draw |S| / 2^32) of S in turn order; with repulsion h the
 // turn pixels 1 .. h-1 positions away on either side leave S.  -1 when D is
 // filled.
-__device__ int spiral_select(const FrState &fs, uint64_t *red) {
+__device__ __forceinline__ int spiral_select(const FrState &fs, uint64_t *red) {
     __shared__ int sh_pos;
     FrCtl *ctl = fs.ctl;
     const int N = fs.N, W = fs.W;
@@ -1039,7 +1051,7 @@ __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_
 // flight, so the loads of their filled-pairs words overlap.  Returns the
 // number of new pairs.
 template <int PF, bool kCntLds>
-__device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, int v, int s, int *cnt) {
+__device__ __forceinline__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, int v, int s, int *cnt) {
     const int N = fs.N, MW = fs.MW;
     int uy = v / W, ux = v - uy * W;
     const uint32_t wv = pk[uy * pkW + ux];
@@ -1099,7 +1111,7 @@ __device__ int fill_from(const FrState &fs, const uint32_t *pk, int pkW, int W, 
 // grandparent, and the grandparent's own grandparent) advances the walk by
 // two ancestors, so the dependent chain of reads is half as long.
 template <int PF, bool kCntLds>
-__device__ int fill_from2(const FrState &fs, const uint32_t *pk, const uint16_t *a2, int W, int v, int s, int *cnt) {
+__device__ __forceinline__ int fill_from2(const FrState &fs, const uint32_t *pk, const uint16_t *a2, int W, int v, int s, int *cnt) {
     constexpr int P2 = PF / 2;
     const int N = fs.N, MW = fs.MW;
     const uint32_t wv = pk[v];
@@ -1116,7 +1128,7 @@ __device__ int fill_from2(const FrState &fs, const uint32_t *pk, const uint16_t 
             return;
         }
         const uint32_t code = tw_code(tcur);
-        a = code == kRootCode ? -1 : cur + code_dy((int)code) * W + code_dx((int)code);
+        a = code == kRootCode ? -1 : cur + code_off((int)code, W);
         b = a < 0 ? -1 : gcur;
         const int ac = a < 0 ? v : a, bc = b < 0 ? v : b;  // in-range addresses
         const uint32_t ta = pk[ac], tb = pk[bc];
@@ -1215,9 +1227,9 @@ __device__ void fr_fill_block(const FrState &fs, const uint32_t *tree, int W, ui
             const uint32_t c1 = tw_code(spk[x]);
             uint16_t g = 0xFFFFu;
             if (c1 != kRootCode) {
-                const int p = x + code_dy((int)c1) * W + code_dx((int)c1);
+                const int p = x + code_off((int)c1, W);
                 const uint32_t c2 = tw_code(spk[p]);
-                if (c2 != kRootCode) g = (uint16_t)(p + code_dy((int)c2) * W + code_dx((int)c2));
+                if (c2 != kRootCode) g = (uint16_t)(p + code_off((int)c2, W));
             }
             a2[x] = g;
         }
@@ -1278,7 +1290,7 @@ struct WalkOut {
 };
 
 template <int PF>
-__device__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v, uint32_t *flags) {
+__device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v, uint32_t *flags) {
     constexpr int kCap = kFillFlagWords * 32;
     int cur = v;
     // the next two ancestors of cur and their words of row v; addresses are
@@ -1356,7 +1368,7 @@ __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, in
 }
 
 template <int CS>
-__device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t *G, const uint32_t *flags,
+__device__ __forceinline__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t *G, const uint32_t *flags,
                            uint32_t *cnt8, int v, int dv, int last, int s) {
     constexpr int kCap = kFillFlagWords * 32;
     uint32_t *mrow = fs.mask + (size_t)v * fs.MW;
@@ -1384,53 +1396,73 @@ __device__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t 
     }
 }
 
-// L[x] = parent(x) | (d(x) - d(parent(x))) << 16 (kNoId at the root) from the
-// tree words T, both in LDS; U pixels per thread at a time, so that their
-// dependent LDS reads overlap.
-__device__ void build_parent_links(const uint32_t *T, uint32_t *L, int N, int W) {
-    constexpr int U = 8;
-    const int nb = (int)blockDim.x;
-    for (int base = threadIdx.x; base < N; base += nb * U) {
-        uint32_t t[U], tp[U];
-        int p[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) t[k] = T[min(base + k * nb, N - 1)];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int x = min(base + k * nb, N - 1);
-            const uint32_t c = tw_code(t[k]);
-            p[k] = c == kRootCode ? -1 : x + code_dy((int)c) * W + code_dx((int)c);
-            tp[k] = T[p[k] < 0 ? x : p[k]];
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (base + k * nb < N)
-                L[base + k * nb] = p[k] < 0 ? kNoId : ((uint32_t)p[k] | ((uint32_t)(tw_dist(t[k]) - tw_dist(tp[k])) << 16));
-    }
+// The link tables of a tree, straight from its words in global memory:
+// L[x] = parent(x) | (d(x) - d(parent(x))) << 16 and G[x] = parent(parent(x))
+// (kNoId where there is none).  The parent's word holds both its distance
+// and its own parent's direction, so one dependent load per pixel gives both
+// tables.  The loads are latency-bound: each thread takes 4 * U pixels at a
+// time (U 16-byte loads, then the 4 * U parents' words), which covers a
+// 128 x 128 image in two round trips of each kind.
+__device__ __forceinline__ void link_words(const uint32_t *__restrict__ tree, int x, uint32_t t, uint32_t tp, int W,
+                                           uint32_t &l, uint32_t &gg) {
+    const uint32_t c = tw_code(t);
+    const int p = x + code_off((int)c, W);
+    const uint32_t cp = tw_code(tp);
+    l = c == kRootCode ? kNoId : ((uint32_t)p | ((uint32_t)(tw_dist(t) - tw_dist(tp)) << 16));
+    gg = (c == kRootCode || cp == kRootCode) ? kNoId : (uint32_t)(p + code_off((int)cp, W));
 }
 
-// G[x] = grandparent(x) (kNoId: none) from L.
-__device__ void build_grandparents(const uint32_t *L, uint16_t *G, int N) {
+__device__ __forceinline__ void build_links(const uint32_t *__restrict__ tree, uint32_t *L, uint16_t *G, int N, int W) {
     constexpr int U = 8;
     const int nb = (int)blockDim.x;
-    for (int base = threadIdx.x; base < N; base += nb * U) {
-        uint32_t p[U], g[U];
+    const int N4 = N / 4;
+    const uint4 *t4p = reinterpret_cast<const uint4 *>(tree);
+    auto parent_of = [&](int x, uint32_t t) {
+        const uint32_t c = tw_code(t);
+        return x + code_off((int)c, W);  // the root's offset is 0
+    };
+    for (int base = threadIdx.x; base < N4; base += nb * U) {
+        uint4 t[U];
+        uint32_t tp[U][4];
 #pragma unroll
-        for (int k = 0; k < U; ++k) p[k] = L[min(base + k * nb, N - 1)] & 0xFFFFu;
+        for (int k = 0; k < U; ++k) t[k] = t4p[min(base + k * nb, N4 - 1)];
 #pragma unroll
-        for (int k = 0; k < U; ++k) g[k] = p[k] == kNoId ? kNoId : (L[p[k]] & 0xFFFFu);
+        for (int k = 0; k < U; ++k) {
+            const int x = 4 * min(base + k * nb, N4 - 1);
+            tp[k][0] = tree[parent_of(x, t[k].x)];
+            tp[k][1] = tree[parent_of(x + 1, t[k].y)];
+            tp[k][2] = tree[parent_of(x + 2, t[k].z)];
+            tp[k][3] = tree[parent_of(x + 3, t[k].w)];
+        }
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (base + k * nb < N) G[base + k * nb] = (uint16_t)g[k];
+        for (int k = 0; k < U; ++k) {
+            const int i = base + k * nb;
+            if (i >= N4) continue;
+            const int x = 4 * i;
+            uint4 l;
+            uint32_t g0, g1, g2, g3;
+            link_words(tree, x, t[k].x, tp[k][0], W, l.x, g0);
+            link_words(tree, x + 1, t[k].y, tp[k][1], W, l.y, g1);
+            link_words(tree, x + 2, t[k].z, tp[k][2], W, l.z, g2);
+            link_words(tree, x + 3, t[k].w, tp[k][3], W, l.w, g3);
+            *reinterpret_cast<uint4 *>(&L[x]) = l;
+            *reinterpret_cast<uint2 *>(&G[x]) = make_uint2(g0 | (g1 << 16), g2 | (g3 << 16));
+        }
+    }
+    for (int x = 4 * N4 + threadIdx.x; x < N; x += nb) {
+        const uint32_t t = tree[x];
+        uint32_t l, gg;
+        link_words(tree, x, t, tree[parent_of(x, t)], W, l, gg);
+        L[x] = l;
+        G[x] = (uint16_t)gg;
     }
 }
 
 // The link fill of one block: pixels chunk * kLanes .. + kLanes, PF pairs of
 // ancestors in flight per walk.  smem: link_fill_lds(N, kLanes) bytes: L (N
-// words), then a region that first holds the tree words and then G, the
-// ancestor counters and the new-pair flags.
+// words), G (N uint16), the ancestor counters and the new-pair flags.
 template <int kLanes = kFillLanes, int PF = 16>
-__device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
+__device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
                                  int chunk) {
     constexpr int CS = fill_cnt_shift(kLanes), kPer = 1 << CS, kBits = 32 / kPer;
     constexpr uint32_t kCntMask = (1u << kBits) - 1u;
@@ -1439,29 +1471,34 @@ __device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W,
     const int s = ctl->s, N = fs.N;
     const int ncw = (N + kPer - 1) / kPer;  // counter words
     uint32_t *L = smem;
-    uint32_t *T = smem + al4w(N);
-    uint16_t *G = (uint16_t *)T;
-    uint32_t *C8 = T + al4w((N + 1) / 2);
+    uint16_t *G = (uint16_t *)(smem + al4w(N));
+    uint32_t *C8 = smem + al4w(N) + al4w((N + 1) / 2);
     uint32_t *FL = C8 + al4w(ncw);
-    copy_to_lds(T, tree, N);
-    __syncthreads();
-    build_parent_links(T, L, N, W);
+    // phase ticks, read by thread 0 when tracing (a traced block also waits
+    // for every walker between the detect and write phases)
+    int64_t ph[6] = {t0, 0, 0, 0, 0, 0};
+    const bool tr0 = fs.trace && threadIdx.x == 0;
+    build_links(tree, L, G, N, W);
+    for (int i = threadIdx.x; i < ncw; i += blockDim.x) C8[i] = 0;
     const int v = chunk * kLanes + (int)threadIdx.x;
     // a complete row has nothing left to fill, whenever it became complete
     const bool walker = (int)threadIdx.x < kLanes && v < N && v != s && fs.count[v] < N;
-    const int dv = walker ? tw_dist(T[v]) : 0;
-    __syncthreads();  // the tree words are no longer needed: their space takes G, counters and flags
-    build_grandparents(L, G, N);
-    for (int i = threadIdx.x; i < ncw; i += blockDim.x) C8[i] = 0;
+    const int dv = walker ? tw_dist(tree[v]) : 0;
     __syncthreads();
+    if (tr0) ph[1] = trace_clock();
     WalkOut o{0, -1, 0};
     uint32_t *flags = FL + (size_t)threadIdx.x * kFillFlagWords;
     if (walker) o = walk_detect<PF>(L, G, fs.mask + (size_t)v * fs.MW, v, flags);
+    if (fs.trace) {
+        __syncthreads();
+        if (tr0) ph[2] = trace_clock();
+    }
     if (o.nnew) {
         walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s);
         atomicAdd(&fs.count[v], o.nnew);
     }
     __syncthreads();
+    if (tr0) ph[3] = trace_clock();
     for (int i = threadIdx.x; i < ncw; i += blockDim.x) {
         const uint32_t c = C8[i];
         if (c) {
@@ -1490,6 +1527,11 @@ __device__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W,
         if (__lane_id() == 0) atomicMax((unsigned long long *)&tr[kTrMaxWalk], (unsigned long long)mw);
         if (threadIdx.x == 0) {
             const int64_t t1 = trace_clock();
+            ph[4] = t1;
+            for (int i = 0; i < 4; ++i)
+                atomicAdd((unsigned long long *)&tr[kTrPhTables + i], (unsigned long long)(ph[i + 1] - ph[i]));
+            atomicMax((unsigned long long *)&tr[kTrPhDetectMax], (unsigned long long)(ph[2] - ph[1]));
+            atomicMax((unsigned long long *)&tr[kTrPhWriteMax], (unsigned long long)(ph[3] - ph[2]));
             atomicAdd((unsigned long long *)&tr[kTrVisits], (unsigned long long)walked);
             atomicAdd((unsigned long long *)&tr[kTrNew], (unsigned long long)tot);
             atomicAdd((unsigned long long *)&tr[kTrWalkers], (unsigned long long)walkers);

@@ -110,7 +110,7 @@ struct FrState {
 };
 
 // Per-step trace fields (int64) of the filling-rate loop.
-constexpr int kTraceFields = 16;
+constexpr int kTraceFields = 24;
 enum TraceField {
     kTrVisits = 0,     // ancestors walked by the fill (pairs tested)
     kTrNew = 1,        // new pairs
@@ -126,7 +126,14 @@ enum TraceField {
     kTrFillBlocks = 11,  // fill blocks that ran
     kTrSpecDone = 12,    // speculative pieces that reached their fixed point
     kTrSpecEnd = 13,     // max over speculative pieces of the end tick
-    kTrHit = 14          // 1: the step's tree came from the cache
+    kTrHit = 14,         // 1: the step's tree came from the cache
+    // link-fill phases, ticks summed over fill blocks (15, 20, 21 unused):
+    kTrPhTables = 16,    // link tables built, counters cleared
+    kTrPhDetect = 17,    // loads-only walks (the block's slowest walker)
+    kTrPhWrite = 18,     // writing walks
+    kTrPhFlush = 19,     // counters flushed, totals
+    kTrPhDetectMax = 22, // slowest block's detect phase
+    kTrPhWriteMax = 23   // slowest block's write phase
 };
 
 // The link fill (the redundancy fill with 16-bit pixel ids in LDS tables).
@@ -141,13 +148,17 @@ constexpr int kFillFlagWords = 12;
 // new pair per walking thread, so 8 bits hold up to 255 walkers and 16 bits
 // the rest.  log2 of the counters per 32-bit word:
 __host__ __device__ constexpr int fill_cnt_shift(int lanes) { return lanes < 256 ? 2 : 1; }
-// LDS of a link-fill block: L (N words), then a region that holds the tree
-// words (N words) and afterwards G (N uint16), the counters and the flags.
+// LDS of a link-fill block: L (N words), G (N uint16), the counters and the
+// flags.
 __host__ __device__ inline size_t link_fill_lds(int N, int lanes = kFillLanes) {
     const size_t per = (size_t)1 << fill_cnt_shift(lanes);
-    const size_t later = al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + per - 1) / per) + (size_t)lanes * kFillFlagWords;
-    return 4 * (al4w(N) + (al4w(N) > later ? al4w(N) : later));
+    return 4 * (al4w(N) + al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + per - 1) / per) +
+                (size_t)lanes * kFillFlagWords);
 }
+
+// Whether propagations without a tree check their edges after the first
+// round by default (else only after the second).
+constexpr int kNaiveCheck1 = 0;
 
 // Launch shapes the autotuner chooses (include/gapd.h, gapd_autotune).
 struct Tuning {
@@ -155,6 +166,7 @@ struct Tuning {
     int walk_pf = 16;             // link fill: ancestor pairs in flight per walk (8 or 16)
     int spec_cap = 32;            // tree modes: new speculative propagations per step (<= kSpecK)
     int naive_pfw = 4;            // naive: lines of weights the sweeps load ahead (4 or 8)
+    int naive_check1 = kNaiveCheck1;  // naive: check the edges after the first round (0 or 1)
 };
 
 // Speculation: each step lists the kSpecK least-filled points whose trees are
@@ -218,9 +230,10 @@ hipError_t launch_prep_batched(const GImgW *w_dev, const uint8_t *imgs_dev, cons
                                int B, int C, int wmode, hipStream_t st);
 
 // Propagations from sources (list or src_base + block) into K rows of out.
-// pfw: the sweeps' weight prefetch depth (0: 4; the autotuner may pick 8).
+// pfw: the sweeps' weight prefetch depth (0: 4; the autotuner may pick 8);
+// check1: check the edges after the first round already.
 hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw = 0);
+                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw = 0, int check1 = kNaiveCheck1);
 
 // Filling-rate method pieces for one image.
 hipError_t launch_fr_init(const FrState &fs, hipStream_t st);
@@ -233,7 +246,7 @@ hipError_t launch_fr_step(const GImg &g, const FrState &fs, int max_rounds, hipS
 // Batched naive: every (image, source) item in one launch.
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line,
                                      size_t lds_bytes, int conn, int32_t *out, int max_rounds, FrCtl *ctl,
-                                     hipStream_t st);
+                                     hipStream_t st, int check1 = kNaiveCheck1);
 // Batched filling rate, images in lockstep: the setup of every image, then
 // steps that each cover every image still running (one select+propagate
 // block per image, then the fills of all images in one launch).  lds is the

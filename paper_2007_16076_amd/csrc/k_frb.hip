@@ -29,8 +29,11 @@ template <int CONN, int S, bool kStageW>
 __global__ __launch_bounds__(kRelaxThreads) void k_fr_step_b(const BImg *imgs, int max_rounds, int *batch_done) {
     extern __shared__ int smem[];
     __shared__ uint64_t red[kRelaxThreads / 64];
-    const BImg &bi = imgs[blockIdx.x];
-    fr_step_block<CONN, S, kStageW>(bi.g, bi.Wp, bi.fr, max_rounds, smem, red, batch_done);
+    // the image's descriptors by value: kept in registers rather than re-read
+    // through a pointer (or copied to the stack)
+    const GImg g = imgs[blockIdx.x].g;
+    const FrState fs = imgs[blockIdx.x].fr;
+    fr_step_block<CONN, S, kStageW>(g, imgs[blockIdx.x].Wp, fs, max_rounds, smem, red, batch_done);
 }
 
 // Batched fill: blockIdx.y is the image, blockIdx.x a chunk of its pixels.
@@ -38,10 +41,10 @@ template <bool kLds, bool kLdsCount>
 __global__ __launch_bounds__(256) void k_fr_fill_b(const BImg *imgs) {
     extern __shared__ uint32_t spk[];
     __shared__ int64_t red[4];
-    const BImg &bi = imgs[blockIdx.y];
-    if ((int)(blockIdx.x * blockDim.x) >= bi.fr.N) return;
-    fr_fill_block<kLds, kLdsCount>(bi.fr, bi.fr.packed, bi.g.W, spk, red, blockIdx.x,
-                                   (bi.fr.N + blockDim.x - 1) / blockDim.x);
+    const FrState fs = imgs[blockIdx.y].fr;
+    if ((int)(blockIdx.x * blockDim.x) >= fs.N) return;
+    fr_fill_block<kLds, kLdsCount>(fs, fs.packed, imgs[blockIdx.y].g.W, spk, red, blockIdx.x,
+                                   (fs.N + blockDim.x - 1) / blockDim.x);
 }
 
 template <int CONN, int S>

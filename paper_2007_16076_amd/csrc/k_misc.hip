@@ -49,7 +49,7 @@ size_t fr_workspace_bytes(int N, bool spec) {
     const size_t MW = ((size_t)N + 31) / 32;
     size_t b = al256((size_t)N * MW * 4) + 7 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
     if (spec)
-        b += al256((size_t)kSpecSlots * N * 4) + al256((size_t)N * 4) + 2 * al256(kSpecSlots * 4) +
+        b += al256((size_t)kSpecSlots * al4w(N) * 4) + al256((size_t)N * 4) + 2 * al256(kSpecSlots * 4) +
              al256(2 * kSpecK * 4);
     return b;
 }
@@ -69,7 +69,7 @@ FrState fr_workspace_layout(void *ws, int N, bool spec) {
     f.sp_in = (int32_t *)p; p += al256((size_t)N * 4);  // a spiral turn has at most N pixels
     f.ctl = (FrCtl *)p; p += al256(sizeof(FrCtl));
     if (spec) {
-        f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * N * 4);
+        f.cache = (uint32_t *)p; p += al256((size_t)kSpecSlots * al4w(N) * 4);
         f.src_slot = (int32_t *)p; p += al256((size_t)N * 4);
         f.slot_src = (int32_t *)p; p += al256(kSpecSlots * 4);
         f.slot_state = (int32_t *)p; p += al256(kSpecSlots * 4);

@@ -13,11 +13,14 @@ namespace {
 // With kGlobal the distance field lives in the output row itself (images too
 // large for LDS); otherwise in LDS, and the row is written once at the end.
 // PFW: the sweeps' weight prefetch depth (0: the default of 4 lines).
+// check1: check the edges after the first round already (smooth images often
+// reach the fixed point in one round, and a check costs far less than a
+// round); else the second round runs unchecked.
 // ---------------------------------------------------------------------------------------------
 template <int CONN, int S, bool kGlobal, int PFW = 0>
 __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, const int32_t *src_list,
                                                               int src_base, int32_t *out, int max_rounds,
-                                                              FrCtl *ctl) {
+                                                              FrCtl *ctl, int check1) {
     extern __shared__ int smem[];
     const int s = src_list ? src_list[blockIdx.x] : src_base + (int)blockIdx.x;
     int32_t *row = out + (size_t)blockIdx.x * g.N;
@@ -27,7 +30,8 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wd + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, S, kGlobal, false, PFW>(g, d, Wd, max_rounds);
+    const int r = relax_block<CONN, S, kGlobal, false, PFW>(g, d, Wd, max_rounds, nullptr, nullptr, nullptr,
+                                                            check1 != 0);
     if (threadIdx.x == 0) {
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
 
 template <int CONN, int S>
 __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg *imgs, int B, int32_t *out,
-                                                                      int max_rounds, FrCtl *ctl) {
+                                                                      int max_rounds, FrCtl *ctl, int check1) {
     extern __shared__ int smem[];
     const int64_t item = (int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
     const int b = find_image(imgs, B, item);
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
     __syncthreads();
     if (threadIdx.x == 0) d[(s / g.W) * Wp + s % g.W] = 0;
     __syncthreads();
-    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds);
+    const int r = relax_block<CONN, S>(g, d, Wp, max_rounds, nullptr, nullptr, nullptr, check1 != 0);
     if (threadIdx.x == 0) {
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
 template <int CONN, int S>
 struct RelaxRows {
     static hipError_t run(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                          int max_rounds, FrCtl *ctl, hipStream_t st, int pfw) {
+                          int max_rounds, FrCtl *ctl, hipStream_t st, int pfw, int check1) {
         const int Wp = lds_row_stride(g.W);
         const size_t lds = (size_t)g.H * Wp * sizeof(int);
         if (lds <= kMaxLds) {
@@ -84,10 +88,10 @@ struct RelaxRows {
             hipError_t e = set_lds(k, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k, dim3(K), dim3(kRelaxThreads), lds, st, g, Wp, src_list, src_base, out,
-                               max_rounds, ctl);
+                               max_rounds, ctl, check1);
         } else {
             hipLaunchKernelGGL((k_relax_rows<CONN, S, true>), dim3(K), dim3(kRelaxThreads), 0, st, g, g.W,
-                               src_list, src_base, out, max_rounds, ctl);
+                               src_list, src_base, out, max_rounds, ctl, check1);
         }
         return hipGetLastError();
     }
@@ -96,14 +100,14 @@ struct RelaxRows {
 template <int CONN, int S>
 struct RelaxRowsBatched {
     static hipError_t run(const BImg *imgs, int B, int64_t n_items, size_t lds, int32_t *out, int max_rounds,
-                          FrCtl *ctl, hipStream_t st) {
+                          FrCtl *ctl, hipStream_t st, int check1) {
         auto k = k_relax_rows_batched<CONN, S>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         const int64_t gx = n_items < 65536 ? n_items : 65536;
         const int64_t gy = (n_items + gx - 1) / gx;
         hipLaunchKernelGGL(k, dim3((unsigned)gx, (unsigned)gy), dim3(kRelaxThreads), lds, st, imgs, B, out,
-                           max_rounds, ctl);
+                           max_rounds, ctl, check1);
         return hipGetLastError();
     }
 };
@@ -112,16 +116,18 @@ struct RelaxRowsBatched {
 
 // ---- launchers ----------------------------------------------------------------------------------
 hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_base, int K, int32_t *out,
-                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw) {
+                             int max_rounds, FrCtl *ctl, hipStream_t st, int pfw, int check1) {
     if (K <= 0) return hipSuccess;
     return dispatch<RelaxRows>(g.conn, g.H > g.W ? g.H : g.W, g, src_list, src_base, K, out, max_rounds, ctl,
-                               st, pfw);
+                               st, pfw, check1);
 }
 
 hipError_t launch_relax_rows_batched(const BImg *imgs_dev, int B, int64_t n_items, int max_line, size_t lds_bytes,
-                                     int conn, int32_t *out, int max_rounds, FrCtl *ctl, hipStream_t st) {
+                                     int conn, int32_t *out, int max_rounds, FrCtl *ctl, hipStream_t st,
+                                     int check1) {
     if (n_items <= 0) return hipSuccess;
-    return dispatch<RelaxRowsBatched>(conn, max_line, imgs_dev, B, n_items, lds_bytes, out, max_rounds, ctl, st);
+    return dispatch<RelaxRowsBatched>(conn, max_line, imgs_dev, B, n_items, lds_bytes, out, max_rounds, ctl, st,
+                                      check1);
 }
 
 }  // namespace gapd

@@ -4,7 +4,7 @@
 //
 // File format (one object per key):
 //   {"gfx950/128x128x1/c4/m1": {"fill_lanes": 128, "walk_pf": 16, "spec_cap": 32,
-//                               "naive_pfw": 4, "ms": 1103.2}, ...}
+//                               "naive_pfw": 4, "naive_check1": 1, "ms": 1103.2}, ...}
 #include <dlfcn.h>
 
 #include <cctype>
@@ -82,6 +82,7 @@ void load_locked() {
         if (field(obj, "walk_pf", &v)) e.t.walk_pf = (int)v;
         if (field(obj, "spec_cap", &v)) e.t.spec_cap = (int)v;
         if (field(obj, "naive_pfw", &v)) e.t.naive_pfw = (int)v;
+        if (field(obj, "naive_check1", &v)) e.t.naive_check1 = (int)v;
         if (field(obj, "ms", &v)) e.ms = v;
         // Shapes the kernels do not have fall back to the defaults.
         const Tuning d;
@@ -89,6 +90,7 @@ void load_locked() {
         if (e.t.walk_pf != 8 && e.t.walk_pf != 16) e.t.walk_pf = d.walk_pf;
         if (e.t.spec_cap < 1 || e.t.spec_cap > kSpecK) e.t.spec_cap = d.spec_cap;
         if (e.t.naive_pfw != 4 && e.t.naive_pfw != 8) e.t.naive_pfw = d.naive_pfw;
+        if (e.t.naive_check1 != 0 && e.t.naive_check1 != 1) e.t.naive_check1 = d.naive_check1;
         if (key.find('/') != std::string::npos) g_cache[key] = e;
         p = o1 + 1;
     }
@@ -105,8 +107,8 @@ void save_locked() {
         char line[512];
         std::snprintf(line, sizeof line,
                       "  \"%s\": {\"fill_lanes\": %d, \"walk_pf\": %d, \"spec_cap\": %d, \"naive_pfw\": %d, "
-                      "\"ms\": %.3f}%s\n",
-                      kv.first.c_str(), t.fill_lanes, t.walk_pf, t.spec_cap, t.naive_pfw, kv.second.ms,
+                      "\"naive_check1\": %d, \"ms\": %.3f}%s\n",
+                      kv.first.c_str(), t.fill_lanes, t.walk_pf, t.spec_cap, t.naive_pfw, t.naive_check1, kv.second.ms,
                       ++i < g_cache.size() ? "," : "");
         f << line;
     }

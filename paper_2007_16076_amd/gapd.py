@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("fill_lanes", ctypes.c_int32), ("walk_pf", ctypes.c_int32), ("spec_cap", ctypes.c_int32),
                 ("naive_pfw", ctypes.c_int32), ("ms", ctypes.c_float), ("ms_default", ctypes.c_float),
-                ("candidates", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("naive_check1", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -223,7 +223,7 @@ class Context:
     def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None,
                   time_kernels: bool = False, step_trace=None):
         """The N x N distances array (device int32) and the call's statistics.
-        step_trace: optional device int64 tensor of 16 * N entries (per-step
+        step_trace: optional device int64 tensor of 24 * N entries (per-step
         counters of the tree modes, see gapd_stats.step_trace)."""
         import torch
         if out is None:
@@ -248,9 +248,9 @@ class Context:
         _check(load_library().gapd_autotune(self._h, mode, _dptr(out), ctypes.byref(t)), self._h)
         return {k: getattr(t, k) for k, _ in Tuning._fields_ if not k.startswith("_")}
 
-    def set_tuning(self, mode: int, fill_lanes=128, walk_pf=16, spec_cap=32, naive_pfw=4) -> None:
+    def set_tuning(self, mode: int, fill_lanes=128, walk_pf=16, spec_cap=32, naive_pfw=4, naive_check1=0) -> None:
         """gapd_set_tuning: pin the launch shapes of `mode` on images of this key."""
-        t = Tuning(fill_lanes, walk_pf, spec_cap, naive_pfw, 0.0, 0.0, 0, 0)
+        t = Tuning(fill_lanes, walk_pf, spec_cap, naive_pfw, 0.0, 0.0, 0, naive_check1)
         _check(load_library().gapd_set_tuning(self._h, mode, ctypes.byref(t)), self._h)
 
     def all_pairs_noalloc(self, mode: int, out, sources_out=None, filled_out=None):

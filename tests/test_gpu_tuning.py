@@ -68,18 +68,19 @@ def test_every_naive_shape_gives_the_same_result(G, torch_mod, oracle_lib):
     img = rng.integers(1, 256, size=(40, 97), dtype=np.uint8)
     ctx = G.Context(img, conn=8)
     ref = oracle_lib.naive(img, conn=8)
-    for pfw in (4, 8):
-        say("naive pfw", pfw)
-        ctx.set_tuning(G.MODE_NAIVE, naive_pfw=pfw)
+    for pfw, c1 in itertools.product((4, 8), (0, 1)):
+        say("naive pfw", pfw, "check1", c1)
+        ctx.set_tuning(G.MODE_NAIVE, naive_pfw=pfw, naive_check1=c1)
         D, _ = ctx.all_pairs(G.MODE_NAIVE, out=poisoned(torch, ctx.N, ctx.N))
         torch.cuda.synchronize()
-        assert np.array_equal(D.cpu().numpy(), ref), pfw
+        assert np.array_equal(D.cpu().numpy(), ref), (pfw, c1)
     ctx.set_tuning(G.MODE_NAIVE)
 
 
 def test_set_tuning_rejects_unsupported_shapes(G, torch_mod):
     ctx = G.Context(np.full((8, 8), 3, dtype=np.uint8))
-    for bad in ({"fill_lanes": 64}, {"walk_pf": 4}, {"spec_cap": 0}, {"spec_cap": 33}, {"naive_pfw": 2}):
+    for bad in ({"fill_lanes": 64}, {"walk_pf": 4}, {"spec_cap": 0}, {"spec_cap": 33}, {"naive_pfw": 2},
+                {"naive_check1": 2}):
         with pytest.raises(G.GapdError):
             ctx.set_tuning(G.MODE_TREE_FILL_FR, **bad)
     with pytest.raises(G.GapdError):
@@ -96,7 +97,7 @@ def test_autotune_writes_the_cache_and_a_correct_D(G, torch_mod, oracle_lib, tmp
     ctx = G.Context(img)
     N = ctx.N
     ref = oracle_lib.naive(img)
-    for mode, ncand in ((G.MODE_NAIVE, 2), (G.MODE_TREE_FILL_FR, 8)):
+    for mode, ncand in ((G.MODE_NAIVE, 4), (G.MODE_TREE_FILL_FR, 8)):
         say("autotune mode", mode)
         out = poisoned(torch, N, N)
         best = ctx.autotune(mode, out=out)
