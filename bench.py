@@ -199,6 +199,9 @@ def fill_trace(ctx, mode, out, path=None):
     nb = np.maximum(t[:, 11], 1)
     for i, k in enumerate(["tables", "detect", "write", "flush"]):
         cols[f"ph_{k}_us"] = t[:, 16 + i] * us / nb  # mean over the step's fill blocks
+    npc = np.maximum(t[:, 8], 1)
+    for i, k in ((15, "stage"), (20, "round"), (21, "store")):
+        cols[f"spec_{k}_us"] = t[:, i] * us / npc  # mean over the step's pieces
     cols["ph_detect_max_us"] = t[:, 22] * us
     cols["ph_write_max_us"] = t[:, 23] * us
     n = st.n_prop

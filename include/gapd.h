@@ -110,9 +110,11 @@ typedef struct {
                                block end, the speculative pieces run, the slowest piece,
                                the select kernel, the fill blocks, the pieces that reached
                                their fixed point, the last piece end, 1 if the step's tree
-                               came from the cache, 0, then the link fill's phases summed
-                               over its workgroups (link tables built, loads-only walks,
-                               writing walks, counters flushed), 0, 0, and the slowest
+                               came from the cache, the speculative pieces' staging
+                               summed over them, then the link fill's phases summed over
+                               its workgroups (link tables built, loads-only walks,
+                               writing walks, counters flushed), the pieces' sweep rounds
+                               and write-backs summed over them, and the slowest
                                workgroup's two walk phases
                                (times in ticks of the device's constant clock,
                                hipDeviceAttributeWallClockRate kHz).  Tracing adds a

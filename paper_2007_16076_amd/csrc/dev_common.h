@@ -153,7 +153,10 @@ __device__ __forceinline__ int sel(int mask, int a, int b) { return (a & mask) |
 
 // Both exclusive scans at once: x = prefix minimum over lanes < l of p,
 // y = suffix minimum over lanes > l of q.  Interleaving the two dependency
-// chains hides most of the DPP and readlane latency.
+// chains hides most of the DPP latency.  The prefix scan crosses the 16-lane
+// rows with the row broadcasts of lanes 15 and 31 and shifts by one lane over
+// the whole wave; the suffix scan takes the first lane of each later row by
+// readlane.
 __device__ __forceinline__ int2 wave_excl_scans(int p, int q, const RowMasks &m) {
     p = min(p, dpp_mov<0x111>(kBig, p));
     q = min(q, dpp_mov<0x101>(kBig, q));
@@ -163,21 +166,24 @@ __device__ __forceinline__ int2 wave_excl_scans(int p, int q, const RowMasks &m)
     q = min(q, dpp_mov<0x104>(kBig, q));
     p = min(p, dpp_mov<0x118>(kBig, p));
     q = min(q, dpp_mov<0x108>(kBig, q));
-    const int a0 = __builtin_amdgcn_readlane(p, 15);
+    // rows 1 and 3 take lane 15 of the row before, rows 2 and 3 lane 31
+    p = min(p, __builtin_amdgcn_update_dpp(kBig, p, 0x142, 0xA, 0xF, false));
     const int b1 = __builtin_amdgcn_readlane(q, 16);
-    const int a1 = __builtin_amdgcn_readlane(p, 31);
     const int b2 = __builtin_amdgcn_readlane(q, 32);
-    const int a2 = __builtin_amdgcn_readlane(p, 47);
     const int b3 = __builtin_amdgcn_readlane(q, 48);
-    int cp = sel(m.ge1, a0, kBig);
-    int cq = sel(m.le0, b1, kBig);
-    cp = min(cp, sel(m.ge2, a1, kBig));
-    cq = min(cq, sel(m.le1, b2, kBig));
-    cp = min(cp, sel(m.ge3, a2, kBig));
-    cq = min(cq, sel(m.le2, b3, kBig));
-    p = min(p, cp);
-    q = min(q, cq);
-    return make_int2(dpp_mov<0x111>(cp, p), dpp_mov<0x101>(cq, q));
+    p = min(p, __builtin_amdgcn_update_dpp(kBig, p, 0x143, 0xC, 0xF, false));
+    const int b23 = min(b2, b3), b123 = min(b1, b23);
+    q = min(q, sel(m.le0, b123, sel(m.le1, b23, sel(m.le2, b3, kBig))));
+    // exclusive: the inclusive value of the lane before (wave_shr:1) / after (wave_shl:1)
+    return make_int2(__builtin_amdgcn_update_dpp(kBig, p, 0x138, 0xF, 0xF, false),
+                     __builtin_amdgcn_update_dpp(kBig, q, 0x130, 0xF, 0xF, false));
+}
+
+// base[idx] with the byte offset computed in 32 bits (arrays under 4 GiB), so
+// that the load takes a scalar base and a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T *__restrict__ base, uint32_t idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (idx * (uint32_t)sizeof(T)));
 }
 
 // Inputs of one line of a sweep, prefetched into registers.
@@ -234,23 +240,26 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
             cur[j] = ok[j] ? v : kInf;
         }
     };
+    // weight and prefix-sum offsets as unsigned 32-bit indices, so that the
+    // loads take a scalar base plus a 32-bit vector offset
     auto load = [&](LineIn<C> &in, int step) {
         const int l = FWD ? step : NL - 1 - step;
         const int top = FWD ? (l > 0 ? l - 1 : 0) : l;  // line holding the cross edges into l
+        const uint32_t lo = (uint32_t)(l * L), to = (uint32_t)(top * L);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            in.P[j] = P[l * L + ec[j]];
-            in.wc[j] = wv[top * L + ec[j]];
+            in.P[j] = ld_off(P, lo + (uint32_t)ec[j]);
+            in.wc[j] = ld_off(wv, to + (uint32_t)ec[j]);
             if (CONN == 8) {
-                const int a = FWD ? wdr[top * L + em[j]] : wdl[l * L + ec[j]];
-                const int b = FWD ? wdl[top * L + ep[j]] : wdr[l * L + ec[j]];
+                const int a = FWD ? ld_off(wdr, to + (uint32_t)em[j]) : ld_off(wdl, lo + (uint32_t)ec[j]);
+                const int b = FWD ? ld_off(wdl, to + (uint32_t)ep[j]) : ld_off(wdr, lo + (uint32_t)ec[j]);
                 in.wm[j] = okm[j] ? a : kInf;
                 in.wp[j] = okp[j] ? b : kInf;
             }
         }
     };
     int prev[C];
-    bool changed = false;
+    uint32_t chg = 0;
     auto process = [&](const LineIn<C> &in, const int (&cur)[C], int step, bool first) {
         const int l = FWD ? step : NL - 1 - step;
         int a[C], t[C];
@@ -283,13 +292,13 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
             u[C - 1 - j] = min(u[C - 1 - j], u[C - j]);
         }
         const int2 ex = wave_excl_scans(t[C - 1], u[0], rm);
+        // Lanes past the end of the line hold kInf: their atomic min on the
+        // clamped address changes nothing, so every store is unconditional.
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             a[j] = ok[j] ? min(min(t[j], ex.x) + in.P[j], min(u[j], ex.y) - in.P[j]) : kInf;
-            if (ok[j]) {
-                if (a[j] < cur[j]) changed = true;
-                atomicMin(&d[l * ls + ec[j] * es], a[j]);
-            }
+            chg |= (uint32_t)(a[j] < cur[j]);
+            atomicMin(&d[l * ls + ec[j] * es], a[j]);
             prev[j] = a[j];
         }
     };
@@ -322,7 +331,7 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
             process(S[(1 + k) % PF], F[(1 + k) % PD], base + k, false);
             loadd(F[(1 + k) % PD], min(base + k + PD, NL - 1));
         }
-    return changed;
+    return chg != 0;
 }
 
 // Neighbour k of pixel (y, x), in ascending pixel-index order:
@@ -360,7 +369,9 @@ __device__ __forceinline__ void neighbour_paths(const GImg &g, const NbW &w, con
     const int yu = up ? y - 1 : y, yd = dn ? y + 1 : y, xl = lf ? x - 1 : x, xr = rt ? x + 1 : x;
     const int du = ldd<G>(&d[yu * Wp + x]), dl = ldd<G>(&d[y * Wp + xl]);
     const int dr = ldd<G>(&d[y * Wp + xr]), dd = ldd<G>(&d[yd * Wp + x]);
-    const int wu = w.wd[yu * W + x], wl = w.wr[y * W + xl], wr = w.wr[y * W + x], wdn = w.wd[y * W + x];
+    const uint32_t ou = (uint32_t)(yu * W), oy = (uint32_t)(y * W);
+    const int wu = ld_off(w.wd, ou + x), wl = ld_off(w.wr, oy + xl), wr = ld_off(w.wr, oy + x),
+              wdn = ld_off(w.wd, oy + x);
     cand[1] = up ? du + wu : kBig;
     cand[3] = lf ? dl + wl : kBig;
     cand[4] = rt ? dr + wr : kBig;
@@ -368,8 +379,8 @@ __device__ __forceinline__ void neighbour_paths(const GImg &g, const NbW &w, con
     if (CONN == 8) {
         const int dul = ldd<G>(&d[yu * Wp + xl]), dur = ldd<G>(&d[yu * Wp + xr]);
         const int ddl = ldd<G>(&d[yd * Wp + xl]), ddr = ldd<G>(&d[yd * Wp + xr]);
-        const int wul = w.wdr[yu * W + xl], wur = w.wdl[yu * W + xr];
-        const int wdl_ = w.wdl[y * W + x], wdr_ = w.wdr[y * W + x];
+        const int wul = ld_off(w.wdr, ou + xl), wur = ld_off(w.wdl, ou + xr);
+        const int wdl_ = ld_off(w.wdl, oy + x), wdr_ = ld_off(w.wdr, oy + x);
         cand[0] = (up && lf) ? dul + wul : kBig;
         cand[2] = (up && rt) ? dur + wur : kBig;
         cand[5] = (dn && lf) ? ddl + wdl_ : kBig;
@@ -1557,6 +1568,7 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
 // the plan has no piece j.
 template <int CONN, int S, bool kStageW>
 __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
+    const int64_t tstart = fs.trace && threadIdx.x == 0 ? trace_clock() : 0;
     FrCtl *ctl = fs.ctl;
     if (j >= ctl->spec_n) return -3;
     const int c = fs.spec_list[j], sl = fs.spec_list[kSpecK + j];
@@ -1596,11 +1608,13 @@ __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem
         }
     }
     __syncthreads();
+    const int64_t tp0 = fs.trace && threadIdx.x == 0 ? trace_clock() : 0;
     bool tree_done = false;
     // One sweep round.  A new propagation never converges in its first round;
     // a resumed field is checked right after it, which saves the round that
     // would otherwise only confirm the fixed point.
     const int r = relax_block<CONN, S, false, true>(g, d, Wp, 1, &w, tree, &tree_done, c < 0);
+    const int64_t tp1 = fs.trace && threadIdx.x == 0 ? trace_clock() : 0;
     if (r >= 0) {
         if (!tree_done) field_check<CONN, false, true>(g, w, d, Wp, tree);
         __threadfence();
@@ -1619,6 +1633,12 @@ __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem
     if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&ctl->rounds, 1ull);
         atomicAdd((unsigned long long *)&ctl->spec_rounds, 1ull);
+        if (fs.trace) {
+            int64_t *tr = fs.trace + (ctl->n_prop - 1) * kTraceFields;
+            atomicAdd((unsigned long long *)&tr[kTrSpecStage], (unsigned long long)(tp0 - tstart));
+            atomicAdd((unsigned long long *)&tr[kTrSpecRound], (unsigned long long)(tp1 - tp0));
+            atomicAdd((unsigned long long *)&tr[kTrSpecStore], (unsigned long long)(trace_clock() - tp1));
+        }
     }
     return r;
 }

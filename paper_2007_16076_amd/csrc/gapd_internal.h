@@ -127,7 +127,10 @@ enum TraceField {
     kTrSpecDone = 12,    // speculative pieces that reached their fixed point
     kTrSpecEnd = 13,     // max over speculative pieces of the end tick
     kTrHit = 14,         // 1: the step's tree came from the cache
-    // link-fill phases, ticks summed over fill blocks (15, 20, 21 unused):
+    kTrSpecStage = 15,   // speculative pieces: weights staged and field loaded (ticks summed over pieces)
+    kTrSpecRound = 20,   // ... the sweep round (and the edge check of a resumed field)
+    kTrSpecStore = 21,   // ... the tree words or the field written back
+    // link-fill phases, ticks summed over fill blocks:
     kTrPhTables = 16,    // link tables built, counters cleared
     kTrPhDetect = 17,    // loads-only walks (the block's slowest walker)
     kTrPhWrite = 18,     // writing walks
