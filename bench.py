@@ -181,10 +181,10 @@ def fill_trace(ctx, mode, out, path=None):
     summary by phase of the run; the per-step table goes to ``path``."""
     import torch
     N = ctx.N
-    tr = torch.zeros(24 * N, dtype=torch.int64, device="cuda")
+    tr = torch.zeros(32 * N, dtype=torch.int64, device="cuda")
     _, st = ctx.all_pairs(mode, out=out, step_trace=tr)
     torch.cuda.synchronize()
-    t = tr.view(N, 24)[: st.n_prop].cpu().numpy().astype(np.float64)
+    t = tr.view(N, 32)[: st.n_prop].cpu().numpy().astype(np.float64)
     us = 1e3 / wall_clock_khz()
     start = (2.0 ** 63 - 1) - t[:, 6]
     span = np.where(t[:, 11] > 0, (t[:, 7] - start) * us, 0.0)
@@ -202,6 +202,8 @@ def fill_trace(ctx, mode, out, path=None):
     npc = np.maximum(t[:, 8], 1)
     for i, k in ((15, "stage"), (20, "round"), (21, "store")):
         cols[f"spec_{k}_us"] = t[:, i] * us / npc  # mean over the step's pieces
+    for i, k in ((24, "pass"), (25, "min"), (26, "sort"), (27, "rest")):
+        cols[f"sel_{k}_us"] = t[:, i] * us
     cols["ph_detect_max_us"] = t[:, 22] * us
     cols["ph_write_max_us"] = t[:, 23] * us
     n = st.n_prop

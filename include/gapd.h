@@ -101,9 +101,9 @@ typedef struct {
                                     likely next sources (not counted in n_prop)          */
     int64_t  n_cache_hits;  /* filling-rate steps whose propagation was such a tree, taken
                                from the cache instead of being propagated again          */
-    int64_t *step_trace;    /* input: nullable DEVICE buffer of 24*N int64, zeroed by the
+    int64_t *step_trace;    /* input: nullable DEVICE buffer of 32*N int64, zeroed by the
                                call; for the filling-rate and extrema modes with the tree
-                               cache, loop step t fills entries 24t..24t+23 with the
+                               cache, loop step t fills entries 32t..32t+31 with the
                                ancestors the fill walked, the new pairs, the longest walk,
                                the pixels that walked, the slowest fill block, the sum over
                                fill blocks, 2^63-1 minus the first block start, the last
@@ -114,8 +114,9 @@ typedef struct {
                                summed over them, then the link fill's phases summed over
                                its workgroups (link tables built, loads-only walks,
                                writing walks, counters flushed), the pieces' sweep rounds
-                               and write-backs summed over them, and the slowest
-                               workgroup's two walk phases
+                               and write-backs summed over them, the slowest workgroup's
+                               two walk phases, the select kernel's phases (pass over the
+                               points, argmin, slot keys and sorts, the rest) and 4 zeros
                                (times in ticks of the device's constant clock,
                                hipDeviceAttributeWallClockRate kHz).  Tracing adds a
                                little work to those kernels.                             */

@@ -862,8 +862,10 @@ __device__ __forceinline__ void wave_sort128(uint64_t &a, uint64_t &b) {
 // goes to fs.spec_list (source, or -1 to continue; then the slot), its
 // length to *n_plan.
 template <int RULE>
-__device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, uint64_t *skeys, int *n_plan) {
+__device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, uint64_t *skeys, int *n_plan,
+                              int64_t *ph = nullptr) {
     constexpr int U = 32;  // three loads each: the whole pass is a few round trips
+    const bool tr0 = ph && threadIdx.x == 0;
     constexpr uint64_t kTop = (1ull << 46) - 1, kPinned = (1ull << 50) - 1;
     const int32_t *aux = sel_aux<RULE>(fs);
     uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
@@ -897,7 +899,9 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
             }
         }
     }
+    if (tr0) ph[0] = trace_clock();
     best = block_min_u64(best, red);
+    if (tr0) ph[1] = trace_clock();
     const int s = key_done<RULE>(fs, best) ? -1 : key_point<RULE>(fs, best);
     if (c1 == best) { c1 = c2; c2 = kNoKey; }
     else if (c2 == best) c2 = kNoKey;
@@ -957,6 +961,7 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
         }
     }
     __syncthreads();
+    if (tr0) ph[2] = trace_clock();
     const int nr = n_run < kSpecK ? n_run : kSpecK;
     if (threadIdx.x < kSpecK) {
         const int j = threadIdx.x;
@@ -989,7 +994,8 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
 // counts the images of a batch whose loop has ended.
 template <int CONN, int S, bool kStageW, bool kSpec = false>
 __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_rounds, int *smem, uint64_t *red,
-                              int *batch_done, uint64_t *keys = nullptr, uint64_t *skeys = nullptr) {
+                              int *batch_done, uint64_t *keys = nullptr, uint64_t *skeys = nullptr,
+                              int64_t *ph = nullptr) {
     FrCtl *ctl = fs.ctl;
     if (ctl->done) return;
     if (threadIdx.x == 0 && fs.filled_out && ctl->n_prop > 0) fs.filled_out[ctl->n_prop - 1] = ctl->filled;
@@ -999,9 +1005,9 @@ __device__ void fr_step_block(const GImg &g, int Wp, const FrState &fs, int max_
         s = spiral_select(fs, red);  // random draws: nothing to speculate on
         if (kSpec && threadIdx.x == 0) n_cand = 0;
     } else if (fs.rule == kRuleExtrema)
-        s = kSpec ? fr_select_spec<kRuleExtrema>(fs, red, keys, skeys, &n_cand) : fr_select<kRuleExtrema>(fs, red);
+        s = kSpec ? fr_select_spec<kRuleExtrema>(fs, red, keys, skeys, &n_cand, ph) : fr_select<kRuleExtrema>(fs, red);
     else
-        s = kSpec ? fr_select_spec<kRuleFilling>(fs, red, keys, skeys, &n_cand) : fr_select<kRuleFilling>(fs, red);
+        s = kSpec ? fr_select_spec<kRuleFilling>(fs, red, keys, skeys, &n_cand, ph) : fr_select<kRuleFilling>(fs, red);
     if (s < 0) {
         if (threadIdx.x == 0) {
             ctl->done = 1;

@@ -110,7 +110,7 @@ struct FrState {
 };
 
 // Per-step trace fields (int64) of the filling-rate loop.
-constexpr int kTraceFields = 24;
+constexpr int kTraceFields = 32;
 enum TraceField {
     kTrVisits = 0,     // ancestors walked by the fill (pairs tested)
     kTrNew = 1,        // new pairs
@@ -136,7 +136,12 @@ enum TraceField {
     kTrPhWrite = 18,     // writing walks
     kTrPhFlush = 19,     // counters flushed, totals
     kTrPhDetectMax = 22, // slowest block's detect phase
-    kTrPhWriteMax = 23   // slowest block's write phase
+    kTrPhWriteMax = 23,  // slowest block's write phase
+    // select kernel phases (ticks; 28..31 unused):
+    kTrSelPass = 24,     // pass over the points (keys, complete-row bitmap)
+    kTrSelMin = 25,      // block argmin
+    kTrSelSort = 26,     // slot keys and candidate sorts
+    kTrSelRest = 27      // speculation plan, step state, propagation on a miss
 };
 
 // The link fill (the redundancy fill with 16-bit pixel ids in LDS tables).

@@ -31,12 +31,19 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, 
     __shared__ uint64_t keys[2 * kRelaxThreads];
     __shared__ uint64_t skeys[kSpecSlots];
     const int64_t t0 = fs.trace ? trace_clock() : 0;
-    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys);
+    int64_t ph[3] = {t0, t0, t0};  // select phases (thread 0, when tracing)
+    fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys,
+                                          fs.trace ? ph : nullptr);
     // thread 0 set the step's state; a step that found D complete records nothing
     if (fs.trace && threadIdx.x == 0 && !fs.ctl->done) {
         int64_t *tr = fs.trace + (fs.ctl->n_prop - 1) * kTraceFields;
-        tr[kTrSelect] = trace_clock() - t0;
+        const int64_t t1 = trace_clock();
+        tr[kTrSelect] = t1 - t0;
         tr[kTrHit] = fs.ctl->tree_slot >= 0;
+        tr[kTrSelPass] = ph[0] - t0;
+        tr[kTrSelMin] = ph[1] - ph[0];
+        tr[kTrSelSort] = ph[2] - ph[1];
+        tr[kTrSelRest] = t1 - ph[2];
     }
 }
 

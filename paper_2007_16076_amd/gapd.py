@@ -223,7 +223,7 @@ class Context:
     def all_pairs(self, mode: int = MODE_NAIVE, out=None, sources_out=None, filled_out=None,
                   time_kernels: bool = False, step_trace=None):
         """The N x N distances array (device int32) and the call's statistics.
-        step_trace: optional device int64 tensor of 24 * N entries (per-step
+        step_trace: optional device int64 tensor of 32 * N entries (per-step
         counters of the tree modes, see gapd_stats.step_trace)."""
         import torch
         if out is None:
