@@ -220,13 +220,17 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
     const int lane = __lane_id();
     const RowMasks rm(lane >> 4);
     const int e0 = lane * C;
-    int ec[C], em[C], ep[C];
+    int ec[C], em[C], ep[C], es_[C];
     bool ok[C], okm[C], okp[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) {
         const int e = e0 + j;
         ok[j] = e < L;
         ec[j] = ok[j] ? e : L - 1;
+        // store address: lanes past the end of the line spread over the line
+        // (their atomic min of kInf changes nothing) instead of all hitting
+        // its last element
+        es_[j] = ok[j] ? e : e % L;
         okm[j] = ok[j] && e > 0;
         okp[j] = e + 1 < L;
         em[j] = okm[j] ? e - 1 : ec[j];
@@ -292,13 +296,13 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
             u[C - 1 - j] = min(u[C - 1 - j], u[C - j]);
         }
         const int2 ex = wave_excl_scans(t[C - 1], u[0], rm);
-        // Lanes past the end of the line hold kInf: their atomic min on the
-        // clamped address changes nothing, so every store is unconditional.
+        // Lanes past the end of the line hold kInf: their atomic min changes
+        // nothing, so every store is unconditional.
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             a[j] = ok[j] ? min(min(t[j], ex.x) + in.P[j], min(u[j], ex.y) - in.P[j]) : kInf;
             chg |= (uint32_t)(a[j] < cur[j]);
-            atomicMin(&d[l * ls + ec[j] * es], a[j]);
+            atomicMin(&d[l * ls + es_[j] * es], a[j]);
             prev[j] = a[j];
         }
     };
