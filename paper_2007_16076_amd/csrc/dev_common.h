@@ -826,30 +826,77 @@ __device__ __forceinline__ int spiral_select(const FrState &fs, uint64_t *red) {
     return turn_pixel(tn, W, pos);
 }
 
+// The value v of lane (lane ^ M).  Exchanges inside a 16-lane row use DPP
+// (quad permutes for M = 1, 2; the two row shifts for M = 4; a row rotation
+// for M = 8), which costs a few cycles; across rows the LDS crossbar
+// (ds_bpermute).
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v) {
+    if constexpr (M == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    } else if constexpr (M == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    } else if constexpr (M == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0xF, false);  // row_shl:4
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+        return (__lane_id() & 4) ? dn : up;
+    } else if constexpr (M == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else {
+        return (uint32_t)__shfl_xor((int)v, M);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t v) {
+    return (uint64_t)xor_lane32<M>((uint32_t)v) | ((uint64_t)xor_lane32<M>((uint32_t)(v >> 32)) << 32);
+}
+
+// One compare-exchange stage of a bitonic sort of 128 keys held two per lane
+// (lane l holds elements 2l and 2l+1), for a stride of 2M >= 2 elements:
+// lane l pairs with lane l ^ M.
+template <int SIZE, int M>
+__device__ __forceinline__ void bitonic_lane_stage(uint64_t &a, uint64_t &b) {
+    const int lane = __lane_id();
+    const bool up = ((2 * lane) & SIZE) == 0;
+    const uint64_t pa = xor_lane<M>(a), pb = xor_lane<M>(b);
+    const bool keep_min = ((lane & M) == 0) == up;
+    a = keep_min ? (pa < a ? pa : a) : (pa > a ? pa : a);
+    b = keep_min ? (pb < b ? pb : b) : (pb > b ? pb : b);
+}
+
+template <int SIZE>
+__device__ __forceinline__ void bitonic_lane_inner(uint64_t &a, uint64_t &b) {
+    const bool up = ((2 * __lane_id()) & SIZE) == 0;
+    const bool sw = (a > b) == up;
+    const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+    a = lo;
+    b = hi;
+}
+
+// The stages of one bitonic merge of blocks of SIZE elements: strides
+// SIZE/2 .. 2 across lanes, then stride 1 inside each lane.
+template <int SIZE, int M>
+__device__ __forceinline__ void bitonic_merge_lanes(uint64_t &a, uint64_t &b) {
+    if constexpr (M >= 1) {
+        bitonic_lane_stage<SIZE, M>(a, b);
+        bitonic_merge_lanes<SIZE, M / 2>(a, b);
+    } else {
+        bitonic_lane_inner<SIZE>(a, b);
+    }
+}
+
 // Ascending bitonic sort of 128 keys held two per lane across one wave
 // (lane l holds elements 2l and 2l+1): 28 compare-exchange stages, the
-// stride-1 ones inside a lane, the others through lane shuffles.
+// stride-1 ones inside a lane, the others as lane exchanges (xor_lane).
 __device__ __forceinline__ void wave_sort128(uint64_t &a, uint64_t &b) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int size = 2; size <= 128; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const bool up = ((2 * lane) & size) == 0;
-            if (stride == 1) {
-                const bool sw = (a > b) == up;
-                const uint64_t lo = sw ? b : a, hi = sw ? a : b;
-                a = lo;
-                b = hi;
-            } else {
-                const int m = stride >> 1;
-                const uint64_t pa = __shfl_xor(a, m), pb = __shfl_xor(b, m);
-                const bool keep_min = ((lane & m) == 0) == up;
-                a = keep_min ? (pa < a ? pa : a) : (pa > a ? pa : a);
-                b = keep_min ? (pb < b ? pb : b) : (pb > b ? pb : b);
-            }
-        }
-    }
+    bitonic_merge_lanes<2, 0>(a, b);
+    bitonic_merge_lanes<4, 1>(a, b);
+    bitonic_merge_lanes<8, 2>(a, b);
+    bitonic_merge_lanes<16, 4>(a, b);
+    bitonic_merge_lanes<32, 8>(a, b);
+    bitonic_merge_lanes<64, 16>(a, b);
+    bitonic_merge_lanes<128, 32>(a, b);
 }
 
 // fr_select, and from the same pass the speculation plan for this step: a
@@ -878,10 +925,10 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
         int c[U], a[U], sl[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const int x = min(base + k * (int)blockDim.x, fs.N - 1);
-            c[k] = fs.count[x];
-            a[k] = aux[x];
-            sl[k] = fs.src_slot[x];
+            const uint32_t x = (uint32_t)min(base + k * (int)blockDim.x, fs.N - 1);
+            c[k] = ld_off(fs.count, x);
+            a[k] = ld_off(aux, x);
+            sl[k] = ld_off(fs.src_slot, x);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {

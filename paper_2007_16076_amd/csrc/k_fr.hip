@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_fr_step_spec(GImg g, int Wp, 
     __shared__ uint64_t keys[2 * kRelaxThreads];
     __shared__ uint64_t skeys[kSpecSlots];
     const int64_t t0 = fs.trace ? trace_clock() : 0;
-    int64_t ph[3] = {t0, t0, t0};  // select phases (thread 0, when tracing)
+    __shared__ int64_t ph[3];  // select phases (thread 0, when tracing)
     fr_step_block<CONN, S, kStageW, true>(g, Wp, fs, max_rounds, smem, red, nullptr, keys, skeys,
                                           fs.trace ? ph : nullptr);
     // thread 0 set the step's state; a step that found D complete records nothing
