@@ -336,7 +336,9 @@ typedef struct {
  * Jobs are admitted first come first served while their bytes fit in the arena
  * and a slot is free (max_slots running jobs); admitted jobs run concurrently
  * on max_slots streams of the current device.  The server owns a scheduler
- * thread until gapd_server_destroy. */
+ * thread until gapd_server_destroy.  The slot streams are non-blocking: work
+ * the caller queued on the arena (a fill, a copy) must be complete before
+ * this call, or it may land on top of the jobs' data. */
 int gapd_server_create(void *arena_dev, size_t arena_bytes, int max_slots, gapd_server **out);
 
 /* Queue a job; never blocks.  The image and sources are copied.  *ticket

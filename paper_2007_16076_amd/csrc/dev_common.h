@@ -186,6 +186,42 @@ __device__ __forceinline__ T ld_off(const T *__restrict__ base, uint32_t idx) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (idx * (uint32_t)sizeof(T)));
 }
 
+// A field of N values in pixel order (row stride W) from global memory into
+// LDS rows of stride Wp, and back: U values per thread per batch, all loads of
+// a batch issued before its stores.  Indices past the end are clamped (a
+// repeated copy of the last value).
+template <int U = 8>
+__device__ __forceinline__ void field_to_lds(int *d, int Wp, const uint32_t *__restrict__ src, int N, int W) {
+    const uint64_t mW = divw_magic(W);
+    const int nb = (int)blockDim.x;
+    for (int base = threadIdx.x; base < N; base += nb * U) {
+        uint32_t t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) t[k] = ld_off(src, (uint32_t)min(base + k * nb, N - 1));
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int v = min(base + k * nb, N - 1), y = divw(v, mW);
+            d[y * Wp + (v - y * W)] = (int)t[k];
+        }
+    }
+}
+
+template <int U = 8>
+__device__ __forceinline__ void field_from_lds(uint32_t *dst, const int *d, int Wp, int N, int W) {
+    const uint64_t mW = divw_magic(W);
+    const int nb = (int)blockDim.x;
+    for (int base = threadIdx.x; base < N; base += nb * U) {
+        int t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int v = min(base + k * nb, N - 1), y = divw(v, mW);
+            t[k] = d[y * Wp + (v - y * W)];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) dst[min(base + k * nb, N - 1)] = (uint32_t)t[k];
+    }
+}
+
 // Inputs of one line of a sweep, prefetched into registers.
 template <int C>
 struct LineIn {
@@ -1658,11 +1694,7 @@ __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem
         __syncthreads();
         if (threadIdx.x == 0) d[(c / g.W) * Wp + c % g.W] = 0;
     } else {
-        const uint64_t mW = divw_magic(g.W);
-        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = divw(v, mW), x = v - y * g.W;
-            d[y * Wp + x] = (int)tree[v];
-        }
+        field_to_lds(d, Wp, tree, g.N, g.W);
     }
     __syncthreads();
     const int64_t tp0 = fs.trace && threadIdx.x == 0 ? trace_clock() : 0;
@@ -1681,11 +1713,7 @@ __device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem
             atomicAdd((unsigned long long *)&ctl->spec_props, 1ull);
         }
     } else {
-        const uint64_t mW = divw_magic(g.W);
-        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = divw(v, mW), x = v - y * g.W;
-            tree[v] = (uint32_t)d[y * Wp + x];
-        }
+        field_from_lds(tree, d, Wp, g.N, g.W);
     }
     if (threadIdx.x == 0) {
         atomicAdd((unsigned long long *)&ctl->rounds, 1ull);

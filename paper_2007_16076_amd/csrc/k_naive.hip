@@ -36,13 +36,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows(GImg g, int Wp, co
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
     }
-    if (!kGlobal) {
-        const uint64_t mW = divw_magic(g.W);
-        for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-            const int y = divw(v, mW), x = v - y * g.W;
-            row[v] = d[y * Wp + x];
-        }
-    }
+    if (!kGlobal) field_from_lds((uint32_t *)row, d, Wp, g.N, g.W);
 }
 
 template <int CONN, int S>
@@ -66,12 +60,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_relax_rows_batched(const BImg
         if (r < 0) atomicExch(&ctl->err, GAPD_ENOCONV);
         atomicAdd((unsigned long long *)&ctl->rounds, (unsigned long long)(r < 0 ? max_rounds : r));
     }
-    int32_t *row = out + bi.out_off + (size_t)s * g.N;
-    const uint64_t mW = divw_magic(g.W);
-    for (int v = threadIdx.x; v < g.N; v += blockDim.x) {
-        const int y = divw(v, mW), x = v - y * g.W;
-        row[v] = d[y * Wp + x];
-    }
+    field_from_lds((uint32_t *)(out + bi.out_off + (size_t)s * g.N), d, Wp, g.N, g.W);
 }
 
 template <int CONN, int S>

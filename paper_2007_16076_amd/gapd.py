@@ -343,6 +343,8 @@ class Server:
     def __init__(self, arena_bytes: int, max_slots: int = 4, arena=None):
         import torch
         self.arena = arena if arena is not None else torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        # the server's streams do not wait for work queued on the arena
+        torch.cuda.synchronize()
         h = ctypes.c_void_p()
         _check(load_library().gapd_server_create(_dptr(self.arena), self.arena.numel(), max_slots, ctypes.byref(h)))
         self._h = h
