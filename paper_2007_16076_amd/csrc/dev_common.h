@@ -1391,10 +1391,15 @@ struct WalkOut {
     int nnew;     // new pairs
     int last;     // position (0-based ancestor index) of the last new pair, -1: none
     int walked;   // ancestors visited
+    int fail;     // position of the first new pair the block's list had no room for (INT_MAX: none)
 };
 
+// The loads-only walk also appends each new pair (ancestor u, walker vi) to
+// the block's list in LDS (list, *lcnt, cap entries): LDS atomics leave the
+// wait counts of the global loads exact.
 template <int PF>
-__device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v, uint32_t *flags) {
+__device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v,
+                                               uint32_t *flags, uint32_t *list, int *lcnt, int cap, int vi) {
     constexpr int kCap = kFillFlagWords * 32;
     int cur = v;
     // the next two ancestors of cur and their words of row v; addresses are
@@ -1412,9 +1417,16 @@ __device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t
     uint32_t wa[PF], wb[PF];
 #pragma unroll
     for (int k = 0; k < PF; ++k) gen(ra[k], rb[k], wa[k], wb[k]);
-    WalkOut o{0, -1, 0};
+    WalkOut o{0, -1, 0, INT_MAX};
     uint32_t acc = 0;
     int pos = 0;
+    auto append = [&](int u, int p) {
+        const int i = atomicAdd(lcnt, 1);
+        if (i < cap)
+            list[i] = (uint32_t)u | ((uint32_t)vi << 16);
+        else
+            o.fail = min(o.fail, p);
+    };
     // one pass over the ring: test each slot, then refill it
     auto group = [&]() {
 #pragma unroll
@@ -1428,6 +1440,10 @@ __device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t
             o.nnew += (int)(fa + fb);
             o.last = (fa | fb) ? pos + (int)fb : o.last;
             o.walked += (int)(ea + eb);
+            if (fa | fb) {  // rare after the first steps
+                if (fa) append(a, pos);
+                if (fb) append(b, pos + 1);
+            }
             pos += 2;
             if ((pos & 31) == 0) {
                 if (pos <= kCap) flags[(pos >> 5) - 1] = acc;
@@ -1471,9 +1487,11 @@ __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, in
     }
 }
 
+// Walk again from v to the last new pair and write the new pairs at
+// positions from `from` on (those the block's list had no room for).
 template <int CS>
 __device__ __forceinline__ void walk_write(const FrState &fs, const uint32_t *L, const uint16_t *G, const uint32_t *flags,
-                           uint32_t *cnt8, int v, int dv, int last, int s) {
+                           uint32_t *cnt8, int v, int dv, int last, int s, int from) {
     constexpr int kCap = kFillFlagWords * 32;
     uint32_t *mrow = fs.mask + (size_t)v * fs.MW;
     int32_t *Drow = fs.D + (size_t)v * fs.N;
@@ -1491,10 +1509,10 @@ __device__ __forceinline__ void walk_write(const FrState &fs, const uint32_t *L,
             na = !((mrow[a >> 5] >> (a & 31)) & 1u);
             nb = b != (int)kNoId && !((mrow[b >> 5] >> (b & 31)) & 1u);
         }
-        if (na) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, a, da, s);
+        if (na && p >= from) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, a, da, s);
         if (b == (int)kNoId) break;
         const int db = da - (int)(L[a] >> 16);
-        if (nb) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, b, db, s);
+        if (nb && p + 1 >= from) write_pair<CS>(fs, mrow, Drow, cnt8, v, dv, b, db, s);
         cur = b;
         dcur = db;
     }
@@ -1578,6 +1596,11 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
     uint16_t *G = (uint16_t *)(smem + al4w(N));
     uint32_t *C8 = smem + al4w(N) + al4w((N + 1) / 2);
     uint32_t *FL = C8 + al4w(ncw);
+    int *DV = (int *)(FL + kLanes * kFillFlagWords);  // each walker's d(s, v)
+    uint32_t *LIST = (uint32_t *)(DV + kLanes);        // new pairs: u | walker << 16
+    const int cap = link_fill_list_cap(N, kLanes);
+    __shared__ int lcnt;
+    if (threadIdx.x == 0) lcnt = 0;
     // phase ticks, read by thread 0 when tracing (a traced block also waits
     // for every walker between the detect and write phases)
     int64_t ph[6] = {t0, 0, 0, 0, 0, 0};
@@ -1588,19 +1611,37 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
     // a complete row has nothing left to fill, whenever it became complete
     const bool walker = (int)threadIdx.x < kLanes && v < N && v != s && fs.count[v] < N;
     const int dv = walker ? tw_dist(tree[v]) : 0;
+    if ((int)threadIdx.x < kLanes) DV[threadIdx.x] = dv;
     __syncthreads();
     if (tr0) ph[1] = trace_clock();
-    WalkOut o{0, -1, 0};
+    WalkOut o{0, -1, 0, INT_MAX};
     uint32_t *flags = FL + (size_t)threadIdx.x * kFillFlagWords;
-    if (walker) o = walk_detect<PF>(L, G, fs.mask + (size_t)v * fs.MW, v, flags);
-    if (fs.trace) {
-        __syncthreads();
-        if (tr0) ph[2] = trace_clock();
+    if (walker) o = walk_detect<PF>(L, G, fs.mask + (size_t)v * fs.MW, v, flags, LIST, &lcnt, cap, (int)threadIdx.x);
+    __syncthreads();
+    if (tr0) ph[2] = trace_clock();
+    // The listed pairs, spread over all threads of the block: each needs
+    // d(s, u) (the tree word of u) and its walker's d(s, v); loads first.
+    {
+        constexpr int U = 4;
+        const int n = min(lcnt, cap), nb = (int)blockDim.x;
+        for (int base = threadIdx.x; base < n; base += nb * U) {
+            uint32_t e[U], tu[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) e[k] = LIST[min(base + k * nb, n - 1)];
+#pragma unroll
+            for (int k = 0; k < U; ++k) tu[k] = ld_off(tree, e[k] & 0xFFFFu);
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (base + k * nb >= n) continue;
+                const int u = (int)(e[k] & 0xFFFFu), wi = (int)(e[k] >> 16), vv = chunk * kLanes + wi;
+                write_pair<CS>(fs, fs.mask + (size_t)vv * fs.MW, fs.D + (size_t)vv * N, C8, vv, DV[wi], u,
+                               tw_dist(tu[k]), s);
+            }
+        }
     }
-    if (o.nnew) {
-        walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s);
-        atomicAdd(&fs.count[v], o.nnew);
-    }
+    // pairs the list had no room for: walk again from the first of them
+    if (o.fail != INT_MAX) walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s, o.fail);
+    if (o.nnew) atomicAdd(&fs.count[v], o.nnew);
     __syncthreads();
     if (tr0) ph[3] = trace_clock();
     for (int i = threadIdx.x; i < ncw; i += blockDim.x) {

@@ -152,16 +152,29 @@ __host__ __device__ inline size_t al4w(size_t n) { return (n + 3) & ~size_t(3); 
 // per ancestor; longer walks fall back to re-reading the filled-pairs matrix).
 constexpr int kFillLanes = 128;
 constexpr int kFillFlagWords = 12;
+// Largest dynamic LDS a workgroup may use.
+constexpr size_t kMaxLds = 160 * 1024 - 1024;
+
 // Per-pixel counters of a link-fill block: one ancestor gains at most one
 // new pair per walking thread, so 8 bits hold up to 255 walkers and 16 bits
 // the rest.  log2 of the counters per 32-bit word:
 __host__ __device__ constexpr int fill_cnt_shift(int lanes) { return lanes < 256 ? 2 : 1; }
-// LDS of a link-fill block: L (N words), G (N uint16), the counters and the
-// flags.
-__host__ __device__ inline size_t link_fill_lds(int N, int lanes = kFillLanes) {
+// LDS of a link-fill block: L (N words), G (N uint16), the counters, the
+// flags, each walker's distance, then the list of new pairs: as many words as
+// remain, up to kFillListMax (at least kFillListMin for the link fill to be
+// used).
+constexpr int kFillListMax = 8192, kFillListMin = 1024;
+__host__ __device__ inline size_t link_fill_base_words(int N, int lanes) {
     const size_t per = (size_t)1 << fill_cnt_shift(lanes);
-    return 4 * (al4w(N) + al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + per - 1) / per) +
-                (size_t)lanes * kFillFlagWords);
+    return al4w(N) + al4w(((size_t)N + 1) / 2) + al4w(((size_t)N + per - 1) / per) +
+           (size_t)lanes * (kFillFlagWords + 1);
+}
+__host__ __device__ inline int link_fill_list_cap(int N, int lanes = kFillLanes) {
+    const size_t base = link_fill_base_words(N, lanes), room = (kMaxLds / 4) > base ? (kMaxLds / 4) - base : 0;
+    return (int)((room < (size_t)kFillListMax ? room : (size_t)kFillListMax) & ~(size_t)3);
+}
+__host__ __device__ inline size_t link_fill_lds(int N, int lanes = kFillLanes) {
+    return 4 * (link_fill_base_words(N, lanes) + (size_t)link_fill_list_cap(N, lanes));
 }
 
 // Whether propagations without a tree check their edges after the first
@@ -267,11 +280,10 @@ hipError_t launch_fr_batched_step(const BImg *imgs_dev, int B, int max_line, int
 
 // LDS row stride for an image of width W (odd, so column walks avoid bank conflicts).
 inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }
-// Largest dynamic LDS a workgroup may use.
-constexpr size_t kMaxLds = 160 * 1024 - 1024;
-// The link fill needs 16-bit pixel ids and its tables in LDS.
+// The link fill needs 16-bit pixel ids and its tables, with a list of at
+// least kFillListMin new pairs, in LDS.
 __host__ __device__ inline bool link_fill_fits(int N, int lanes = kFillLanes) {
-    return N >= 1 && N < (int)kNoId && link_fill_lds(N, lanes) <= kMaxLds;
+    return N >= 1 && N < (int)kNoId && link_fill_list_cap(N, lanes) >= kFillListMin;
 }
 
 }  // namespace gapd
