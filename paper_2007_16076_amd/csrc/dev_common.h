@@ -1397,7 +1397,10 @@ struct WalkOut {
 // The loads-only walk also appends each new pair (ancestor u, walker vi) to
 // the block's list in LDS (list, *lcnt, cap entries): LDS atomics leave the
 // wait counts of the global loads exact.
-template <int PF>
+// kG: L holds parent | weight << 16 and G the grandparents; otherwise G is the
+// parent table alone (the compact tables) and the grandparent is the
+// parent's parent, one more dependent LDS read.
+template <int PF, bool kG = true>
 __device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t *G, const uint32_t *mrow, int v,
                                                uint32_t *flags, uint32_t *list, int *lcnt, int cap, int vi) {
     constexpr int kCap = kFillFlagWords * 32;
@@ -1406,7 +1409,14 @@ __device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t
     // clamped into range so that every load is issued
     auto gen = [&](int &a, int &b, uint32_t &ma, uint32_t &mb) {
         const int cc = cur < 0 ? v : cur;
-        const int pa = (int)(L[cc] & 0xFFFFu), pb = (int)G[cc];
+        int pa, pb;
+        if constexpr (kG) {
+            pa = (int)(L[cc] & 0xFFFFu);
+            pb = (int)G[cc];
+        } else {
+            pa = (int)G[cc];
+            pb = (int)G[pa == (int)kNoId ? cc : pa];
+        }
         a = (cur < 0 || pa == (int)kNoId) ? -1 : pa;
         b = (a < 0 || pb == (int)kNoId) ? -1 : pb;
         ma = mrow[(a < 0 ? v : a) >> 5];
@@ -1473,7 +1483,7 @@ __device__ __forceinline__ WalkOut walk_detect(const uint32_t *L, const uint16_t
 // Pair (u, v) is new: D(u,v) = D(v,u) = dv - du, both matrix bits, counts
 // (u's in the block's LDS counters, 1 << CS per word, never the source's:
 // its row is completed by block 0).
-template <int CS>
+template <int CS, bool kGlobalCnt = false>
 __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, int32_t *Drow, uint32_t *cnt, int v,
                                            int dv, int u, int du, int s) {
     constexpr int kPer = 1 << CS, kBits = 32 / kPer;
@@ -1483,7 +1493,10 @@ __device__ __forceinline__ void write_pair(const FrState &fs, uint32_t *mrow, in
     atomicOr(&mrow[u >> 5], 1u << (u & 31));
     if (u != s) {
         atomicOr(&fs.mask[(size_t)u * fs.MW + (v >> 5)], 1u << (v & 31));
-        atomicAdd(&cnt[u >> CS], 1u << ((u & (kPer - 1)) * kBits));
+        if constexpr (kGlobalCnt)
+            atomicAdd(&fs.count[u], 1);
+        else
+            atomicAdd(&cnt[u >> CS], 1u << ((u & (kPer - 1)) * kBits));
     }
 }
 
@@ -1516,6 +1529,53 @@ __device__ __forceinline__ void walk_write(const FrState &fs, const uint32_t *L,
         cur = b;
         dcur = db;
     }
+}
+
+// The compact tables' walk again from v to the last new pair, writing the
+// pairs at positions from `from` on; d(s, u) comes from u's tree word.
+__device__ __forceinline__ void walk_write_compact(const FrState &fs, const uint16_t *P, const uint32_t *tree,
+                                                   const uint32_t *flags, int v, int dv, int last, int s, int from) {
+    constexpr int kCap = kFillFlagWords * 32;
+    uint32_t *mrow = fs.mask + (size_t)v * fs.MW;
+    int32_t *Drow = fs.D + (size_t)v * fs.N;
+    int cur = v;
+    for (int p = 0; p <= last; ++p) {
+        const int u = (int)P[cur];
+        if (u == (int)kNoId) break;
+        bool nu;
+        if (p < kCap)
+            nu = (flags[p >> 5] >> (p & 31)) & 1u;
+        else
+            nu = !((mrow[u >> 5] >> (u & 31)) & 1u);
+        if (nu && p >= from) write_pair<0, true>(fs, mrow, Drow, nullptr, v, dv, u, tw_dist(tree[u]), s);
+        cur = u;
+    }
+}
+
+// The parent table of a tree from its words in global memory (kNoId at the
+// root), 4 pixels per 16-byte load, U loads in flight per thread.
+__device__ __forceinline__ void build_parents(const uint32_t *__restrict__ tree, uint16_t *P, int N, int W) {
+    constexpr int U = 8;
+    const int nb = (int)blockDim.x;
+    const int N4 = N / 4;
+    typedef const __attribute__((address_space(1))) u32x4 *gptr4;
+    const gptr4 t4p = (gptr4)tree;
+    auto par = [&](int x, uint32_t t) -> uint32_t {
+        const uint32_t c = tw_code(t);
+        return c == kRootCode ? kNoId : (uint32_t)(x + code_off((int)c, W));
+    };
+    for (int base = threadIdx.x; base < N4; base += nb * U) {
+        u32x4 t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) t[k] = t4p[min(base + k * nb, N4 - 1)];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = min(base + k * nb, N4 - 1), x = 4 * i;
+            const uint32_t p0 = par(x, t[k].x), p1 = par(x + 1, t[k].y), p2 = par(x + 2, t[k].z), p3 = par(x + 3, t[k].w);
+            *reinterpret_cast<uint2 *>(&P[x]) = make_uint2(p0 | (p1 << 16), p2 | (p3 << 16));
+        }
+    }
+    for (int x = 4 * N4 + threadIdx.x; x < N; x += nb) P[x] = (uint16_t)par(x, tree[x]);
 }
 
 // The link tables of a tree, straight from its words in global memory:
@@ -1583,7 +1643,10 @@ __device__ __forceinline__ void build_links(const uint32_t *__restrict__ tree, u
 // The link fill of one block: pixels chunk * kLanes .. + kLanes, PF pairs of
 // ancestors in flight per walk.  smem: link_fill_lds(N, kLanes) bytes: L (N
 // words), G (N uint16), the ancestor counters and the new-pair flags.
-template <int kLanes = kFillLanes, int PF = 16>
+// kCompact: the compact tables for images whose full tables do not fit LDS:
+// the parent table alone (G), no L, the counts added straight to global
+// memory; d(s, u) always comes from the tree words.
+template <int kLanes = kFillLanes, int PF = 16, bool kCompact = false>
 __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32_t *tree, int W, uint32_t *smem, int64_t *red,
                                  int chunk) {
     constexpr int CS = fill_cnt_shift(kLanes), kPer = 1 << CS, kBits = 32 / kPer;
@@ -1591,21 +1654,24 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
     const FrCtl *ctl = fs.ctl;
     const int64_t t0 = fs.trace ? trace_clock() : 0;
     const int s = ctl->s, N = fs.N;
-    const int ncw = (N + kPer - 1) / kPer;  // counter words
+    const int ncw = kCompact ? 0 : (N + kPer - 1) / kPer;  // counter words
     uint32_t *L = smem;
-    uint16_t *G = (uint16_t *)(smem + al4w(N));
-    uint32_t *C8 = smem + al4w(N) + al4w((N + 1) / 2);
+    uint16_t *G = (uint16_t *)(kCompact ? smem : smem + al4w(N));
+    uint32_t *C8 = kCompact ? smem + al4w((N + 1) / 2) : smem + al4w(N) + al4w((N + 1) / 2);
     uint32_t *FL = C8 + al4w(ncw);
     int *DV = (int *)(FL + kLanes * kFillFlagWords);  // each walker's d(s, v)
     uint32_t *LIST = (uint32_t *)(DV + kLanes);        // new pairs: u | walker << 16
-    const int cap = link_fill_list_cap(N, kLanes);
+    const int cap = kCompact ? compact_fill_list_cap(N, kLanes) : link_fill_list_cap(N, kLanes);
     __shared__ int lcnt;
     if (threadIdx.x == 0) lcnt = 0;
     // phase ticks, read by thread 0 when tracing (a traced block also waits
     // for every walker between the detect and write phases)
     int64_t ph[6] = {t0, 0, 0, 0, 0, 0};
     const bool tr0 = fs.trace && threadIdx.x == 0;
-    build_links(tree, L, G, N, W);
+    if constexpr (kCompact)
+        build_parents(tree, G, N, W);
+    else
+        build_links(tree, L, G, N, W);
     for (int i = threadIdx.x; i < ncw; i += blockDim.x) C8[i] = 0;
     const int v = chunk * kLanes + (int)threadIdx.x;
     // a complete row has nothing left to fill, whenever it became complete
@@ -1616,7 +1682,8 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
     if (tr0) ph[1] = trace_clock();
     WalkOut o{0, -1, 0, INT_MAX};
     uint32_t *flags = FL + (size_t)threadIdx.x * kFillFlagWords;
-    if (walker) o = walk_detect<PF>(L, G, fs.mask + (size_t)v * fs.MW, v, flags, LIST, &lcnt, cap, (int)threadIdx.x);
+    if (walker)
+        o = walk_detect<PF, !kCompact>(L, G, fs.mask + (size_t)v * fs.MW, v, flags, LIST, &lcnt, cap, (int)threadIdx.x);
     __syncthreads();
     if (tr0) ph[2] = trace_clock();
     // The listed pairs, spread over all threads of the block: each needs
@@ -1634,13 +1701,18 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
             for (int k = 0; k < U; ++k) {
                 if (base + k * nb >= n) continue;
                 const int u = (int)(e[k] & 0xFFFFu), wi = (int)(e[k] >> 16), vv = chunk * kLanes + wi;
-                write_pair<CS>(fs, fs.mask + (size_t)vv * fs.MW, fs.D + (size_t)vv * N, C8, vv, DV[wi], u,
-                               tw_dist(tu[k]), s);
+                write_pair<CS, kCompact>(fs, fs.mask + (size_t)vv * fs.MW, fs.D + (size_t)vv * N, C8, vv, DV[wi], u,
+                                         tw_dist(tu[k]), s);
             }
         }
     }
     // pairs the list had no room for: walk again from the first of them
-    if (o.fail != INT_MAX) walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s, o.fail);
+    if (o.fail != INT_MAX) {
+        if constexpr (kCompact)
+            walk_write_compact(fs, G, tree, flags, v, dv, o.last, s, o.fail);
+        else
+            walk_write<CS>(fs, L, G, flags, C8, v, dv, o.last, s, o.fail);
+    }
     if (o.nnew) atomicAdd(&fs.count[v], o.nnew);
     __syncthreads();
     if (tr0) ph[3] = trace_clock();

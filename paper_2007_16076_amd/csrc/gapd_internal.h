@@ -176,6 +176,20 @@ __host__ __device__ inline int link_fill_list_cap(int N, int lanes = kFillLanes)
 __host__ __device__ inline size_t link_fill_lds(int N, int lanes = kFillLanes) {
     return 4 * (link_fill_base_words(N, lanes) + (size_t)link_fill_list_cap(N, lanes));
 }
+// The compact tables (images whose full tables do not fit): the parent table
+// (N uint16), the flags, each walker's distance, then the list; the counts
+// go straight to global memory.  256 walking threads per block.
+constexpr int kCompactLanes = 256;
+__host__ __device__ inline size_t compact_fill_base_words(int N, int lanes = kCompactLanes) {
+    return al4w(((size_t)N + 1) / 2) + (size_t)lanes * (kFillFlagWords + 1);
+}
+__host__ __device__ inline int compact_fill_list_cap(int N, int lanes = kCompactLanes) {
+    const size_t base = compact_fill_base_words(N, lanes), room = kMaxLds / 4 > base ? kMaxLds / 4 - base : 0;
+    return (int)((room < (size_t)kFillListMax ? room : (size_t)kFillListMax) & ~(size_t)3);
+}
+__host__ __device__ inline size_t compact_fill_lds(int N, int lanes = kCompactLanes) {
+    return 4 * (compact_fill_base_words(N, lanes) + (size_t)compact_fill_list_cap(N, lanes));
+}
 
 // Whether propagations without a tree check their edges after the first
 // round by default (else only after the second).
@@ -284,6 +298,9 @@ inline int lds_row_stride(int W) { return (W & 1) ? W : W + 1; }
 // least kFillListMin new pairs, in LDS.
 __host__ __device__ inline bool link_fill_fits(int N, int lanes = kFillLanes) {
     return N >= 1 && N < (int)kNoId && link_fill_list_cap(N, lanes) >= kFillListMin;
+}
+__host__ __device__ inline bool compact_fill_fits(int N) {
+    return N >= 1 && N < (int)kNoId && compact_fill_list_cap(N) >= kFillListMin;
 }
 
 }  // namespace gapd

@@ -59,6 +59,7 @@ __global__ __launch_bounds__(256) void k_fr_fill(FrState fs, int W) {
 // in flight per walk (the autotuner's choice), the walk with a grandparent
 // table (kFillA2) or the plain walk with the tree words in LDS (kFillTree).
 constexpr int kFillTree = 0, kFillA2 = 1, kFillLinks = 2;  // kFillLinks + (lanes == 256) + 2 * (pf == 8)
+constexpr int kFillCompact = 6;  // the compact tables (parent table only, counts in global memory)
 constexpr int fill_links_variant(int lanes, int pf) { return kFillLinks + (lanes == 256 ? 1 : 0) + (pf == 8 ? 2 : 0); }
 constexpr int variant_lanes(int v) { return ((v - kFillLinks) & 1) ? 256 : 128; }
 constexpr int variant_pf(int v) { return ((v - kFillLinks) & 2) ? 8 : 16; }
@@ -89,7 +90,9 @@ __global__ __launch_bounds__(256) void k_fr_fill_spec(GImg g, int Wp, FrState fs
     }
     const int slot = fs.ctl->tree_slot;
     const uint32_t *tree = slot >= 0 ? slot_tree(fs, slot) : fs.packed;
-    if constexpr (kFill >= kFillLinks) {
+    if constexpr (kFill == kFillCompact) {
+        fill_links_block<kCompactLanes, 16, true>(fs, tree, g.W, (uint32_t *)smem, red, blockIdx.x - kSpecK);
+    } else if constexpr (kFill >= kFillLinks) {
         fill_links_block<variant_lanes(kFill), variant_pf(kFill)>(fs, tree, g.W, (uint32_t *)smem, red,
                                                                  blockIdx.x - kSpecK);
     } else {
@@ -186,6 +189,13 @@ struct FrStep {
                     e = launch_links<true>(g, Wp, fs, max_rounds, st, ll, lanes, pf);
                 else
                     e = launch_links<false>(g, Wp, fs, max_rounds, st, ll, lanes, pf);
+            } else if (compact_fill_fits(g.N)) {
+                const size_t cl = std::max(sp, compact_fill_lds(g.N));
+                const int cb = (g.N + kCompactLanes - 1) / kCompactLanes;
+                if (lds + wbytes <= kMaxLds)
+                    e = launch_fill_spec<true, false, kFillCompact>(g, Wp, fs, max_rounds, st, cl, cb);
+                else
+                    e = launch_fill_spec<false, false, kFillCompact>(g, Wp, fs, max_rounds, st, cl, cb);
             } else if (a2 <= kMaxLds && g.N < 0xFFFF) {
                 if (lds + wbytes <= kMaxLds)
                     e = launch_fill_spec<true, false, kFillA2>(g, Wp, fs, max_rounds, st, std::max(sp, a2), blocks2);
