@@ -935,6 +935,68 @@ __device__ __forceinline__ void wave_sort128(uint64_t &a, uint64_t &b) {
     bitonic_merge_lanes<128, 32>(a, b);
 }
 
+// The pass of the select with the speculation plan, spread over many
+// workgroups (its own launch before the step kernel): each thread takes 4
+// points, so each wave holds 4 runs of 64 consecutive points (one ballot per
+// run rebuilds the complete-row bitmap); each wave writes its minimum key to
+// fs.part[w] and its kSelCand smallest candidate keys (points whose row is
+// incomplete and that have no cache slot; each lane keeps its best two) to
+// fs.part[nw + w * kSelCand ...], in increasing order.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+    v = min(v, xor_lane<32>(v));
+    v = min(v, xor_lane<16>(v));
+    v = min(v, xor_lane<8>(v));
+    v = min(v, xor_lane<4>(v));
+    v = min(v, xor_lane<2>(v));
+    v = min(v, xor_lane<1>(v));
+    return v;
+}
+
+template <int RULE>
+__device__ void sel_part_block(const FrState &fs) {
+    if (fs.ctl->done) return;
+    constexpr int U = 4;
+    const int32_t *aux = sel_aux<RULE>(fs);
+    const int N = fs.N, nb = (int)blockDim.x;
+    const int base = (int)blockIdx.x * nb * U + (int)threadIdx.x;
+    int c[U], a[U], sl[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint32_t x = (uint32_t)min(base + k * nb, N - 1);
+        c[k] = ld_off(fs.count, x);
+        a[k] = ld_off(aux, x);
+        sl[k] = ld_off(fs.src_slot, x);
+    }
+    uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int x = base + k * nb;
+        // the complete-row bitmap, rebuilt from the counts (the link fill adds
+        // to the counts without watching them reach N)
+        const uint64_t fb = __ballot(x < N && c[k] >= N);
+        if (__lane_id() == 0 && x < N) {
+            fs.full[x >> 5] = (uint32_t)fb;
+            if (x + 32 < N) fs.full[(x >> 5) + 1] = (uint32_t)(fb >> 32);
+        }
+        if (x >= N) continue;
+        const uint64_t key = sel_key<RULE>(fs, x, c[k], a[k]);
+        best = key < best ? key : best;
+        if (sl[k] < 0 && c[k] < N) {
+            if (key < c1) { c2 = c1; c1 = key; }
+            else if (key < c2) c2 = key;
+        }
+    }
+    const int nw = (int)gridDim.x * (nb >> 6), w = (int)blockIdx.x * (nb >> 6) + ((int)threadIdx.x >> 6);
+    best = wave_min_u64(best);
+    if (__lane_id() == 0) fs.part[w] = best;
+#pragma unroll 1
+    for (int r = 0; r < kSelCand; ++r) {
+        const uint64_t m = wave_min_u64(c1);
+        if (m != kNoKey && c1 == m) { c1 = c2; c2 = kNoKey; }
+        if (__lane_id() == 0) fs.part[nw + w * kSelCand + r] = m;
+    }
+}
+
 // fr_select, and from the same pass the speculation plan for this step: a
 // list of at most kSpecK propagation pieces for the fill launch.  First every
 // running propagation continues (those whose source's row became complete
@@ -951,39 +1013,23 @@ __device__ __forceinline__ void wave_sort128(uint64_t &a, uint64_t &b) {
 template <int RULE>
 __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, uint64_t *skeys, int *n_plan,
                               int64_t *ph = nullptr) {
-    constexpr int U = 32;  // three loads each: the whole pass is a few round trips
     const bool tr0 = ph && threadIdx.x == 0;
     constexpr uint64_t kTop = (1ull << 46) - 1, kPinned = (1ull << 50) - 1;
     const int32_t *aux = sel_aux<RULE>(fs);
     uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
-    const int step = blockDim.x * U;
-    for (int base = threadIdx.x; base < fs.N; base += step) {
-        int c[U], a[U], sl[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const uint32_t x = (uint32_t)min(base + k * (int)blockDim.x, fs.N - 1);
-            c[k] = ld_off(fs.count, x);
-            a[k] = ld_off(aux, x);
-            sl[k] = ld_off(fs.src_slot, x);
+    // the partial pass (sel_part_block) left each wave's minimum and best
+    // candidates: the minimum over the minima, and each thread's best two of
+    // the candidates it reads
+    {
+        const int nw = sel_part_waves(fs.N);
+        for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+            const uint64_t k = fs.part[i];
+            best = k < best ? k : best;
         }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int x = base + k * (int)blockDim.x;
-            // The complete-row bitmap, rebuilt from the counts: the link fill
-            // adds to the counts without watching them reach N.  A wave's
-            // lanes hold 64 consecutive points.
-            const uint64_t fb = __ballot(x < fs.N && c[k] >= fs.N);
-            if (__lane_id() == 0 && x < fs.N) {
-                fs.full[x >> 5] = (uint32_t)fb;
-                if (x + 32 < fs.N) fs.full[(x >> 5) + 1] = (uint32_t)(fb >> 32);
-            }
-            if (x >= fs.N) continue;
-            const uint64_t key = sel_key<RULE>(fs, x, c[k], a[k]);
-            best = key < best ? key : best;
-            if (sl[k] < 0 && c[k] < fs.N) {
-                if (key < c1) { c2 = c1; c1 = key; }
-                else if (key < c2) c2 = key;
-            }
+        for (int i = threadIdx.x; i < nw * kSelCand; i += blockDim.x) {
+            const uint64_t key = fs.part[nw + i];
+            if (key < c1) { c2 = c1; c1 = key; }
+            else if (key < c2) c2 = key;
         }
     }
     if (tr0) ph[0] = trace_clock();

@@ -100,6 +100,7 @@ struct FrState {
     int32_t *slot_src;
     int32_t *slot_state;       // free, ready (tree words) or running (a partial distance field)
     int32_t *spec_list;
+    uint64_t *part;            // the partial select pass: sel_part_waves(N) minima, then kSelCand keys per wave
     int32_t *dbuf;             // N: distances of the setup propagations
     uint64_t *gtree;           // general graphs: N tree entries, distance << 32 | parent (-1 at the root)
     int32_t *D;                // N * N output
@@ -154,6 +155,12 @@ constexpr int kFillLanes = 128;
 constexpr int kFillFlagWords = 12;
 // Largest dynamic LDS a workgroup may use.
 constexpr size_t kMaxLds = 160 * 1024 - 1024;
+
+// The partial select pass: 256-thread workgroups of 4 points per thread,
+// kSelCand candidates kept per wave.
+constexpr int kSelCand = 8;
+__host__ __device__ inline int sel_part_blocks(int N) { return (N + 1023) / 1024; }
+__host__ __device__ inline int sel_part_waves(int N) { return 4 * sel_part_blocks(N); }
 
 // Per-pixel counters of a link-fill block: one ancestor gains at most one
 // new pair per walking thread, so 8 bits hold up to 255 walkers and 16 bits
@@ -272,6 +279,8 @@ hipError_t launch_relax_rows(const GImg &g, const int32_t *src_list, int src_bas
 
 // Filling-rate method pieces for one image.
 hipError_t launch_fr_init(const FrState &fs, hipStream_t st);
+// The partial select pass of the speculative step (before its step kernel).
+hipError_t launch_sel_part(const FrState &fs, hipStream_t st);
 hipError_t launch_fr_setup(const GImg &g, const FrState &fs, int max_rounds, hipStream_t st);
 // One loop step: select + propagate + tree (one workgroup), then the fill.
 // If mid is given it is recorded between the two launches.

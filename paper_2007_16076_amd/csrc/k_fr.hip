@@ -167,6 +167,10 @@ struct FrStep {
         // kernel to hold its sort keys beside the field
         const bool spec = fs.cache && pk <= kMaxLds && lds + kSpecSortLds <= kMaxLds;
         const size_t extra = spec ? kSpecSortLds : 0;
+        if (spec) {
+            const hipError_t ep = launch_sel_part(fs, st);
+            if (ep != hipSuccess) return ep;
+        }
         hipError_t e = lds + wbytes + extra <= kMaxLds
                            ? launch_step<true>(g, Wp, fs, max_rounds, st, lds + wbytes, spec)
                            : launch_step<false>(g, Wp, fs, max_rounds, st, lds, spec);

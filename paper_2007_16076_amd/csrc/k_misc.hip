@@ -23,6 +23,11 @@ __global__ void k_prefix_batched(const GImgW *ws) {
     prefix_lines(w, threadIdx.x, blockDim.x);
 }
 
+template <int RULE>
+__global__ __launch_bounds__(256) void k_sel_part(FrState fs) {
+    sel_part_block<RULE>(fs);
+}
+
 __global__ void k_fr_init(FrState fs) { fr_init_range(fs, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x); }
 
 }  // namespace
@@ -50,7 +55,7 @@ size_t fr_workspace_bytes(int N, bool spec) {
     size_t b = al256((size_t)N * MW * 4) + 7 * al256((size_t)N * 4) + al256(sizeof(FrCtl));
     if (spec)
         b += al256((size_t)kSpecSlots * al4w(N) * 4) + al256((size_t)N * 4) + 2 * al256(kSpecSlots * 4) +
-             al256(2 * kSpecK * 4);
+             al256(2 * kSpecK * 4) + al256((size_t)sel_part_waves(N) * (1 + kSelCand) * 8);
     return b;
 }
 
@@ -73,12 +78,22 @@ FrState fr_workspace_layout(void *ws, int N, bool spec) {
         f.src_slot = (int32_t *)p; p += al256((size_t)N * 4);
         f.slot_src = (int32_t *)p; p += al256(kSpecSlots * 4);
         f.slot_state = (int32_t *)p; p += al256(kSpecSlots * 4);
-        f.spec_list = (int32_t *)p;
+        f.spec_list = (int32_t *)p; p += al256(2 * kSpecK * 4);
+        f.part = (uint64_t *)p;
     }
     return f;
 }
 
 // ---- launchers ----------------------------------------------------------------------------------
+hipError_t launch_sel_part(const FrState &fs, hipStream_t st) {
+    if (fs.rule == kRuleExtrema)
+        hipLaunchKernelGGL(k_sel_part<kRuleExtrema>, dim3(sel_part_blocks(fs.N)), dim3(256), 0, st, fs);
+    else
+        hipLaunchKernelGGL(k_sel_part<kRuleFilling>, dim3(sel_part_blocks(fs.N)), dim3(256), 0, st, fs);
+    return hipGetLastError();
+}
+
+
 hipError_t launch_prep(const GImgW &w, const uint8_t *img_dev, int C, int wmode, hipStream_t st) {
     const int blocks = (w.N + 255) / 256;
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, w, img_dev, C, wmode);
