@@ -332,10 +332,12 @@ def single_image_line(args, workload, img, conn, desc, fr=True):
         # one propagation writing N tree words.
         step_bytes = 12.0 * N + 4.0 * N * (n_prop - hits) / max(n_prop, 1)
         roof_step = roofline_hbm(step_bytes, step_ms)
-        roof_step.update(kernel="k_fr_step_spec (least-filled select and speculation plan; one propagation + "
-                                "tree on a cache miss; one workgroup)",
+        t_part, t_step = measured_traffic(workload, "k_sel_part<"), measured_traffic(workload, "k_fr_step_spec<")
+        roof_step.update(kernel="k_sel_part + k_fr_step_spec (least-filled select: the pass over the points in "
+                                "many workgroups, then the argmin, speculation plan and, on a cache miss, one "
+                                "propagation + tree in one workgroup)",
                          algorithmic_bytes_per_launch=round(step_bytes), avg_launch_ms=round(step_ms, 5),
-                         traffic=measured_traffic(workload, "k_fr_step_spec<"))
+                         traffic=(t_part + t_step) if t_part is not None and t_step is not None else None)
         roof_step["alu"] = alu_side(step_ops, step_ms, workload, "k_fr_step_spec<")
     else:
         ach = step_ops / (step_ms * 1e-3) / 1e12
