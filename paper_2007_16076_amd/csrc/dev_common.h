@@ -1017,6 +1017,17 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
     constexpr uint64_t kTop = (1ull << 46) - 1, kPinned = (1ull << 50) - 1;
     const int32_t *aux = sel_aux<RULE>(fs);
     uint64_t best = kNoKey, c1 = kNoKey, c2 = kNoKey;
+    // The slots' state (the first two waves, one slot each) does not depend
+    // on the selected point: its loads go out first, beside the partials'.
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    int src = -1, st = kSlotFree, cs = 0, as = 0;
+    if (wave < kSpecSlots / 64) {
+        src = fs.slot_src[threadIdx.x];
+        st = fs.slot_state[threadIdx.x];
+        const int sc = src >= 0 ? src : 0;
+        cs = fs.count[sc];
+        as = aux[sc];
+    }
     // the partial pass (sel_part_block) left each wave's minimum and best
     // candidates: the minimum over the minima, and each thread's best two of
     // the candidates it reads
@@ -1040,16 +1051,13 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
     else if (c2 == best) c2 = kNoKey;
     // slots (kSpecSlots = 128, the first two waves): running ones continue,
     // the others get an eviction key
-    const int wave = threadIdx.x >> 6, lane = __lane_id();
     __shared__ int n_run;
     if (threadIdx.x == 0) n_run = 0;
     __syncthreads();
     uint64_t e0 = ~0ull, e1 = ~0ull;
     if (wave < kSpecSlots / 64) {
         const int t = threadIdx.x;
-        const int src = fs.slot_src[t];
-        const int st = fs.slot_state[t];
-        const int cs = src >= 0 ? fs.count[src] : 0;
+        if (src < 0) cs = 0;
         uint64_t keep;
         if (st == kSlotRunning && cs < fs.N) {
             keep = kPinned;
@@ -1063,7 +1071,7 @@ __device__ int fr_select_spec(const FrState &fs, uint64_t *red, uint64_t *keys, 
         } else if (src == s) {
             keep = kPinned;
         } else {
-            keep = cs >= fs.N ? 1 : 2 + (kTop - key_heur<RULE>(sel_key<RULE>(fs, src, cs, aux[src])));
+            keep = cs >= fs.N ? 1 : 2 + (kTop - key_heur<RULE>(sel_key<RULE>(fs, src, cs, as)));
         }
         // two slot keys per lane: slot t goes to element t of the wave pair
         skeys[t] = (keep << 8) | (uint64_t)t;
