@@ -244,9 +244,11 @@ struct LineIn {
 // by default: a lone workgroup per compute unit wants a deeper ring to cover
 // the L2 latency), the field values at most 4 lines ahead, so they are read
 // as late as possible; all addresses are clamped into the image, so the loads
-// are unconditional.  Returns true if this wave lowered a value it had read.
+// are unconditional.  FULL says that every line has exactly 64 * C elements,
+// so no lane owns a slot past its end and the clamps drop out.  Returns true
+// if this wave lowered a value it had read.
 // ---------------------------------------------------------------------------------------------
-template <int CONN, int C, bool FWD, bool G, int PFW = 0>
+template <int CONN, int C, bool FWD, bool G, int PFW = 0, bool FULL = false>
 __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, const uint16_t *__restrict__ wv,
                       const uint16_t *__restrict__ wdr, const uint16_t *__restrict__ wdl,
                       const int32_t *__restrict__ P) {
@@ -261,7 +263,7 @@ __device__ __forceinline__ bool sweep(int *d, int ls, int es, int NL, int L, con
 #pragma unroll
     for (int j = 0; j < C; ++j) {
         const int e = e0 + j;
-        ok[j] = e < L;
+        ok[j] = FULL || e < L;
         ec[j] = ok[j] ? e : L - 1;
         // store address: lanes past the end of the line spread over the line
         // (their atomic min of kInf changes nothing) instead of all hitting
@@ -497,25 +499,33 @@ __device__ uint32_t parent_code(const GImg &g, const int *d, int Wp, int y, int 
 //
 // PFW is the sweeps' weight prefetch depth (0: the default).  With
 // check_first the edge check also runs after the first round: a field resumed
-// from an earlier round may already be the fixed point.
-template <int CONN, int S, bool G = false, bool TREE = false, int PFW = 0>
+// from an earlier round may already be the fixed point.  FULLOK allows the
+// sweeps' full-line variant (more code; a kernel that inlines several
+// propagations turns it off to stay within its registers).
+template <int CONN, int S, bool G = false, bool TREE = false, int PFW = 0, bool FULLOK = true>
 __device__ __forceinline__ int relax_block(const GImg &g, int *d, int Wp, int max_rounds, const NbW *nw = nullptr,
                                           uint32_t *tree = nullptr, bool *tree_done = nullptr,
                                           bool check_first = false) {
     constexpr int C = S >= 64 ? S / 64 : 1;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
+    // lines that fill every lane slot (rows of length W, columns of length H)
+    const bool full_rows = FULLOK && S >= 64 && g.W == 64 * C, full_cols = FULLOK && S >= 64 && g.H == 64 * C;
     int rounds = 0;
     for (;;) {
         bool ch = false;
         if (wave == 0)
-            ch = sweep<CONN, C, true, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
+            ch = full_rows ? sweep<CONN, C, true, G, PFW, true>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P)
+                           : sweep<CONN, C, true, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
         else if (wave == 1)
-            ch = sweep<CONN, C, false, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
+            ch = full_rows ? sweep<CONN, C, false, G, PFW, true>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P)
+                           : sweep<CONN, C, false, G, PFW>(d, Wp, 1, g.H, g.W, g.wd, g.wdr, g.wdl, g.P);
         else if (wave == 2)
-            ch = sweep<CONN, C, true, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
+            ch = full_cols ? sweep<CONN, C, true, G, PFW, true>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP)
+                           : sweep<CONN, C, true, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
         else if (wave == 3)
-            ch = sweep<CONN, C, false, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
+            ch = full_cols ? sweep<CONN, C, false, G, PFW, true>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP)
+                           : sweep<CONN, C, false, G, PFW>(d, 1, Wp, g.W, g.H, g.cwv, g.cwdr, g.cwdl, g.cP);
         ++rounds;
         if (!__syncthreads_or(ch)) break;
         // A first round that changed anything is almost never the fixed point
@@ -613,7 +623,7 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
         if (y == 0 || y == H - 1 || x == 0 || x == W - 1) d[y * Wp + x] = 0;
     }
     __syncthreads();
-    int r1 = relax_block<CONN, S>(g, d, Wp, max_rounds);
+    int r1 = relax_block<CONN, S, false, false, 0, false>(g, d, Wp, max_rounds);
     // argmax with ties to the smallest index: minimise (INF - d, index)
     uint64_t best = ~0ull;
     for (int v = threadIdx.x; v < N; v += blockDim.x) {
@@ -627,7 +637,7 @@ __device__ void fr_setup_block(const GImg &g, int Wp, const FrState &fs, int *d,
     __syncthreads();
     if (threadIdx.x == 0) d[(c / W) * Wp + c % W] = 0;
     __syncthreads();
-    int r2 = relax_block<CONN, S>(g, d, Wp, max_rounds);
+    int r2 = relax_block<CONN, S, false, false, 0, false>(g, d, Wp, max_rounds);
     for (int v = threadIdx.x; v < N; v += blockDim.x) {
         const int y = v / W, x = v - y * W;
         fs.dbuf[v] = d[y * Wp + x];
@@ -1827,7 +1837,7 @@ __device__ __forceinline__ void fill_links_block(const FrState &fs, const uint32
 // reached the fixed point, -1 when the field goes back to the slot, -3 when
 // the plan has no piece j.
 template <int CONN, int S, bool kStageW>
-__device__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
+__device__ __forceinline__ int fr_spec_block(const GImg &g, int Wp, const FrState &fs, int *smem, int j) {
     const int64_t tstart = fs.trace && threadIdx.x == 0 ? trace_clock() : 0;
     FrCtl *ctl = fs.ctl;
     if (j >= ctl->spec_n) return -3;
