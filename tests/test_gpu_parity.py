@@ -61,8 +61,10 @@ def run_fr(G, torch, img, conn):
 
 # ------------------------------------------------------------------------------------- naive
 
+# (40, 64), (64, 40), (50, 128), (128, 50): one side fills every lane slot of its
+# size class, so the sweeps along it take the full-line variant and the others not.
 SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (5, 9), (32, 32), (33, 65), (70, 3), (3, 70), (64, 64), (65, 64),
-          (17, 130)]
+          (17, 130), (40, 64), (64, 40), (50, 128), (128, 50)]
 
 
 @pytest.mark.parametrize("conn", [4, 8])
@@ -116,7 +118,7 @@ def test_filling_rate_golden(G, torch_mod, name):
 @pytest.mark.parametrize("conn", [4, 8])
 @pytest.mark.parametrize("shape,bands", [((1, 1), 1), ((1, 9), 1), ((9, 1), 1), ((6, 7), 1), ((11, 13), 1),
                                          ((16, 16), 1), ((25, 25), 1), ((9, 12), 3), ((20, 7), 8),
-                                         ((32, 32), 1)])
+                                         ((32, 32), 1), ((40, 64), 1), ((64, 40), 1)])
 def test_filling_rate_matches_oracle(G, torch_mod, oracle_lib, shape, bands, conn):
     say("fr", shape, bands, conn)
     img = rand_img(shape[0] * 31 + shape[1] + bands + conn, *shape, c=bands, lo=0 if bands > 1 else 1)
